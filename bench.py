@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the Householder-reflector hot path on one MI355X.
+
+Default workload (the headline metric): Q X with Q = H_1 ... H_64 on
+N = 2^18 vectors of length n = 4096, synthetic Gaussian data resident in HBM,
+through the C ABI of libhh.so.  The compact-WY form in BF16 on the matrix
+cores is the reported value; the fused FP32 sequential-reflector kernel on
+the same shape is timed beside it.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one library call over the whole batch (reflector setup included).
+Prints one JSON line.  Other workloads (--workload) exist for measurement runs.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+MFMA_BF16_TFLOPS = 2500.0      # dense
+FP32_VALU_TFLOPS = 78.6        # unpacked FP32 FMA (packed FP32 is switched off)
+FP64_VALU_TFLOPS = 78.6
+
+WORKLOADS = {
+    # name: (op, n, h, N, compute, description)
+    "qx_n4096_h64": ("apply", 4096, 64, 1 << 18, "bf16",
+                     "Q X, n=4096, h=64, N=2^18; compact-WY BF16 (FP32 accumulate)"),
+    "qx_n4096_h64_fused": ("apply", 4096, 64, 1 << 18, "f32",
+                           "Q X, n=4096, h=64, N=2^18; fused sequential FP32"),
+    "sym_n1024_h10": ("sym", 1024, 10, 1 << 20, "f32",
+                      "Q diag(lam) Q^T X, n=1024, h=10, N=2^20; fused FP32"),
+    "mahal_n512_h9": ("mahal", 512, 9, 1 << 22, "f32",
+                      "Mahalanobis distances, n=512, h=9, N=2^22 pairs; fused FP32"),
+    "mahal_fb_n512_h9": ("mahal_fb", 512, 9, 1 << 22, "f32",
+                         "Mahalanobis forward + backward to U and lam, n=512, h=9, N=2^22; fused FP32"),
+    "qx_n64_h4_f64": ("apply", 64, 4, 1024, "f64",
+                      "Q X, n=64, h=4, N=1024; fused FP64"),
+}
+DEFAULT = "qx_n4096_h64"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def algorithmic(op, n, h, N, io_bytes, param_bytes=4):
+    """Bytes (one read of each input, one write of each output) and flops
+    (operation counts of the paper: 4nh per Q x, (8h+1)n per symmetric
+    product; (4h+3)n per distance) for one call over N vectors."""
+    if op == "apply":
+        return 2 * n * io_bytes * N, 4 * n * h * N
+    if op == "sym":
+        return 2 * n * io_bytes * N, (8 * h + 1) * n * N
+    if op == "mahal":
+        return (2 * n * io_bytes + param_bytes) * N, (4 * h + 3) * n * N
+    if op == "mahal_fb":
+        fwd = (2 * n * io_bytes + param_bytes) * N
+        bwd = (2 * n * io_bytes + param_bytes) * N
+        return fwd + bwd, ((4 * h + 3) * n + 14 * n * h + 6 * n) * N
+    raise ValueError(op)
+
+
+def source_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key, src_paths):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        with open(p) as f:
+            table = json.load(f)
+        e = table.get(kernel_key)
+        if not e or e.get("source_hash") != source_hash(src_paths):
+            return None
+        return e.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs "
+                          "are not part of this build (--gpus must be 1)"}))
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_1811_07624_amd as P
+
+    op, n, h, N, comp, desc = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    tdt = {"f32": torch.float32, "f64": torch.float64, "bf16": torch.bfloat16,
+           "f16": torch.float16}[comp]
+    io_dt = tdt
+    pdt = torch.float64 if comp == "f64" else torch.float32
+
+    U = torch.tensor(synth.reflectors(n, h, seed=0), dtype=pdt, device=dev)
+    lam = torch.tensor(synth.eig_uniform(n, seed=0), dtype=pdt, device=dev)
+    X = synth.device_gaussian((N, n), seed=0, stream=synth.STREAM_X, device=dev, dtype=io_dt)
+    Xb = None
+    w = None
+    if op in ("mahal", "mahal_fb"):
+        Xb = synth.device_gaussian((N, n), seed=0, stream=synth.STREAM_XB, device=dev, dtype=io_dt)
+    if op == "mahal_fb":
+        w = synth.device_gaussian((N,), seed=0, stream=synth.STREAM_W, device=dev, dtype=pdt)
+    Y = torch.empty_like(X) if op in ("apply", "sym") else None
+    torch.cuda.synchronize()
+
+    def step():
+        if op == "apply":
+            P.apply_raw(U, X, compute=tdt, out=Y)
+        elif op == "sym":
+            P.sym_raw(U, lam, X, compute=tdt, out=Y)
+        elif op == "mahal":
+            P.mahal_raw(U, lam, X, Xb)
+        else:
+            P.mahal_raw(U, lam, X, Xb)
+            P.mahal_bwd_raw(U, lam, X, Xb, w, need_dX=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [a.elapsed_time(b) for a, b in evs]  # ms per call, on the launch stream
+    ms_ev = float(np.mean(per))
+    ms_wall = wall * 1e3 / args.steps
+    ms_step = max(ms_ev, 0.0) if args.steps else float("nan")
+    value = N / (ms_wall * 1e-3)
+
+    io_bytes = {"f32": 4, "f64": 8, "bf16": 2, "f16": 2}[comp]
+    abytes, aflops = algorithmic(op, n, h, N, io_bytes, 8 if comp == "f64" else 4)
+    if comp in ("bf16", "f16"):
+        bound, peak, unit, ach = "hbm", HBM_PEAK_GBS, "GB/s", abytes / (ms_ev * 1e-3) / 1e9
+    else:
+        t_hbm = abytes / (HBM_PEAK_GBS * 1e9)
+        t_alu = aflops / ((FP64_VALU_TFLOPS if comp == "f64" else FP32_VALU_TFLOPS) * 1e12)
+        if t_alu > t_hbm:
+            bound, peak, unit = "alu", (FP64_VALU_TFLOPS if comp == "f64" else FP32_VALU_TFLOPS), "TFLOP/s"
+            ach = aflops / (ms_ev * 1e-3) / 1e12
+        else:
+            bound, peak, unit = "hbm", HBM_PEAK_GBS, "GB/s"
+            ach = abytes / (ms_ev * 1e-3) / 1e9
+    kernel_src = {"bf16": ["paper_1811_07624_amd/csrc/hh_wy.hip"],
+                  "f16": ["paper_1811_07624_amd/csrc/hh_wy.hip"]}.get(
+        comp, ["paper_1811_07624_amd/csrc/hh_fused.hip", "paper_1811_07624_amd/csrc/hh_internal.h"])
+    traffic = measured_traffic(args.workload, kernel_src)
+
+    out = {
+        "metric": "vectors/s for Q.X at n=4096,h=64 (BF16 compact-WY vs FP32 fused)",
+        "value": value,
+        "unit": "vectors/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": comp,
+        "data": "synthetic (seeded Gaussian data, Gaussian unit reflectors)",
+        "config": {"workload": args.workload, "description": desc, "n": n, "h": h, "N": N,
+                   "op": op},
+        "roofline": {"bound": bound, "achieved": ach, "peak": peak, "unit": unit,
+                     "frac": ach / peak, "traffic": traffic,
+                     "kernel_ms_events": ms_ev, "algorithmic_bytes": abytes,
+                     "algorithmic_flops": aflops},
+    }
+
+    # accuracy on a sample of vectors, and the oracle's own speed on it
+    if not args.no_cpu:
+        import oracle
+        Uh = U.double().cpu().numpy()
+        lh = lam.double().cpu().numpy()
+        S = min(N, 64)
+        Xs = X[:S].double().cpu().numpy()
+        t = time.perf_counter()
+        if op == "apply":
+            ref = oracle.apply(Uh, Xs)
+        elif op == "sym":
+            ref = oracle.sym(Uh, lh, Xs)
+        else:
+            ref = oracle.mahal(Uh, lh, Xs, Xb[:S].double().cpu().numpy())
+        t1 = time.perf_counter() - t
+        # size a sample that takes about cpu_seconds
+        S2 = int(min(N, max(S, S * args.cpu_seconds / max(t1, 1e-4))))
+        Xs2 = X[:S2].double().cpu().numpy()
+        t = time.perf_counter()
+        if op == "apply":
+            oracle.apply(Uh, Xs2)
+        elif op == "sym":
+            oracle.sym(Uh, lh, Xs2)
+        elif op == "mahal":
+            oracle.mahal(Uh, lh, Xs2, Xb[:S2].double().cpu().numpy())
+        else:
+            Xbs = Xb[:S2].double().cpu().numpy()
+            oracle.mahal(Uh, lh, Xs2, Xbs)
+            oracle.mahal_bwd(Uh, lh, Xs2, Xbs, w[:S2].double().cpu().numpy())
+        tcpu = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": S2 / tcpu, "unit": "vectors/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"first {S2} of {N} vectors of the same batch, FP64"}
+        if op in ("apply", "sym"):
+            Yg = Y[:S].double().cpu().numpy()
+            err = float(np.max(np.linalg.norm(Yg - ref, axis=1) / np.linalg.norm(ref, axis=1)))
+        else:
+            dg = P.mahal_raw(U, lam, X[:S], Xb[:S]).double().cpu().numpy()
+            err = float(np.max(np.abs(dg - ref) / np.abs(ref)))
+        out["max_rel_err_sample"] = err
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,182 @@
+/*
+ * hh.h -- C ABI of the Householder-reflector transform library (libhh.so).
+ *
+ * The library applies an orthonormal operator built from a few Householder
+ * reflectors to large batches of vectors on an AMD Instinct MI355X (gfx950):
+ *
+ *   H_k = I - 2 uh_k uh_k^T,  uh_k = u_k / ||u_k||_2        (paper Sec. II-A, eq. 2)
+ *   Q   = H_1 H_2 ... H_h                                   (eq. 1, in the order
+ *                                                            Result 3 uses, eq. theU2)
+ *   Y = Q X,   Y = Q^T X                                    (Sec. II-A: 4nh ops/vector)
+ *   Y = Q diag(lam) Q^T X                                   (Sec. III-A, eq. thesbar,
+ *                                                            D = I: (8h+1)n ops/vector)
+ *   d_j = || diag(sqrt(lam)) Q^T (xa_j - xb_j) ||^2         (Sec. IV-C: the learned
+ *                                                            metric L = sqrt(Lambda) U)
+ * and the gradients of each with respect to X, the reflector vectors and lam.
+ * Q^{-1} = Q^T, so the solve of Sec. I is hh_apply_T; the inverse of the
+ * symmetric form is hh_sym_apply with 1/lam.
+ *
+ * Reflector vectors are normalised inside the library in FP64.  A zero column
+ * u_k gives H_k = I (Sec. II-B, after Result 1) and a zero gradient.  Any
+ * h >= 0 is accepted (h = 0 is the identity); the bounds h < n/2 and
+ * h < n/4 of Secs. II-A and III-A are efficiency bounds, not validity bounds.
+ *
+ * ---------------------------------------------------------------------------
+ * Layout (column-major, BLAS style; every data pointer is a DEVICE pointer):
+ *   U(i,k) = U[i + k*ldu]   i < n, k < h      reflector k is column k
+ *   X(i,j) = X[i + j*ldx]   i < n, j < N      vector j is contiguous
+ *   lam, dlam: n contiguous; dist, ddist: N contiguous.
+ *   In torch terms U is an (h, n) tensor and X an (N, n) tensor.
+ *
+ * Ownership: the caller owns every buffer.  The library never allocates or
+ * frees device memory; scratch space is the caller's workspace `ws` of at least
+ * hh_workspace_size() bytes, 256-byte aligned.  Outputs dU and dlam are
+ * overwritten, not accumulated.  Calls are stream-ordered and asynchronous:
+ * each validates its arguments on the host, enqueues kernels on `stream` and
+ * returns; outputs are valid once the stream has passed the call.  Calls that
+ * share a workspace must be ordered on one stream.  No exception crosses the
+ * ABI.  NaN and Inf propagate and are not detected.
+ *
+ * Numbers (hh_desc): the FUSED algorithm computes in F64 or F32 with parameters
+ * and data of that same type.  The WY algorithm (compact form Q = I - Y T Y^T,
+ * prior art of Bischof & Van Loan and Schreiber & Van Loan, not the paper)
+ * computes in BF16 or F16 on the matrix cores with FP32 accumulation, F32
+ * parameters, and BF16/F16 (matching compute) or F32 data.  HH_ALGO_AUTO picks
+ * FUSED for F64/F32 compute and WY for BF16/F16 compute.  Any other
+ * combination returns HH_ERR_UNSUPPORTED.
+ *
+ * Validation (synchronous, before anything is enqueued): n >= 1, h >= 0,
+ * N >= 0; every leading dimension >= n; required pointers non-null when
+ * N > 0 (U may be null only when h == 0); ws_bytes >= the required size
+ * (else HH_ERR_WORKSPACE).  N == 0 is a no-op for the forward calls; the
+ * backward calls then write zero dU/dlam.  Y may alias X exactly (Y == X and
+ * ldy == ldx) in hh_apply, hh_apply_T and hh_sym_apply; any other overlap
+ * is undefined.  hh_last_error() returns a thread-local message for the last
+ * failing call on the calling thread.
+ */
+#ifndef HH_H_
+#define HH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#if defined(__GNUC__)
+#define HH_API __attribute__((visibility("default")))
+#else
+#define HH_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HH_OK = 0,
+    HH_ERR_INVALID_ARG = 1,
+    HH_ERR_UNSUPPORTED = 2,
+    HH_ERR_WORKSPACE = 3,
+    HH_ERR_HIP = 4
+} hh_status;
+
+typedef enum { HH_F64 = 0, HH_F32 = 1, HH_BF16 = 2, HH_F16 = 3 } hh_dtype;
+
+typedef enum { HH_ALGO_AUTO = 0, HH_ALGO_FUSED = 1, HH_ALGO_WY = 2 } hh_algo;
+
+typedef enum {
+    HH_OP_APPLY = 0,
+    HH_OP_APPLY_T = 1,
+    HH_OP_SYM = 2,
+    HH_OP_MAHAL = 3,
+    HH_OP_APPLY_BWD = 4,
+    HH_OP_APPLY_T_BWD = 5,
+    HH_OP_SYM_BWD = 6,
+    HH_OP_MAHAL_BWD = 7
+} hh_op;
+
+typedef struct {
+    int64_t n;              /* vector length (rows of U and X)                   */
+    int64_t h;              /* number of reflectors (columns of U)               */
+    int64_t N;              /* number of vectors (pairs for the Mahalanobis ops) */
+    hh_dtype param_dtype;   /* U, lam, dist, ddist, dU, dlam                     */
+    hh_dtype io_dtype;      /* X, Xa, Xb, Y, dY, dX, dXa, dXb                    */
+    hh_dtype compute_dtype; /* FUSED: F64 | F32 ; WY: BF16 | F16                 */
+    hh_algo algo;
+} hh_desc;
+
+/* Bytes of workspace that `op` needs for descriptor `d` (0 is possible). */
+HH_API hh_status hh_workspace_size(hh_op op, const hh_desc *d, size_t *bytes);
+
+/* Y = Q X  (Sec. II-A, eqs. 1-2).  Y is n x N with leading dimension ldy. */
+HH_API hh_status hh_apply(const hh_desc *d, const void *U, int64_t ldu, const void *X,
+                   int64_t ldx, void *Y, int64_t ldy, void *ws, size_t ws_bytes,
+                   hipStream_t stream);
+
+/* Y = Q^T X = H_h ... H_1 X  (Sec. II-A; also the solve Q^{-1} X). */
+HH_API hh_status hh_apply_T(const hh_desc *d, const void *U, int64_t ldu, const void *X,
+                     int64_t ldx, void *Y, int64_t ldy, void *ws, size_t ws_bytes,
+                     hipStream_t stream);
+
+/* Y = Q diag(lam) Q^T X  (Sec. III-A, eq. thesbar with D = I). */
+HH_API hh_status hh_sym_apply(const hh_desc *d, const void *U, int64_t ldu,
+                       const void *lam, const void *X, int64_t ldx, void *Y,
+                       int64_t ldy, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* dist[j] = sum_i lam_i ((Q^T (xa_j - xb_j))_i)^2  (Sec. IV-C).  N pairs.
+ * dist has param_dtype.  lam >= 0 is the metric's meaning but is not checked. */
+HH_API hh_status hh_mahalanobis(const hh_desc *d, const void *U, int64_t ldu,
+                         const void *lam, const void *Xa, int64_t lda,
+                         const void *Xb, int64_t ldb, void *dist, void *ws,
+                         size_t ws_bytes, hipStream_t stream);
+
+/* Gradients of L with upstream dY = dL/dY for Y = Q X (hh_apply_backward) or
+ * Y = Q^T X (hh_apply_T_backward).  dX (nullable, n x N, lddx) receives
+ * dL/dX; dU (nullable, n x h, lddu, param_dtype) receives dL/dU for the raw U:
+ * dU_k = (I - uh_k uh_k^T) (dL/duh_k) / ||u_k||; at unit norm this is the
+ * tangent projection the paper applies to its gradient before each step on
+ * the sphere (Sec. III-B, after eq. gradient); zero for a zero column.  The
+ * sum over the N vectors is deterministic for a given device and shape. */
+HH_API hh_status hh_apply_backward(const hh_desc *d, const void *U, int64_t ldu,
+                            const void *X, int64_t ldx, const void *dY,
+                            int64_t lddy, void *dX, int64_t lddx, void *dU,
+                            int64_t lddu, void *ws, size_t ws_bytes,
+                            hipStream_t stream);
+HH_API hh_status hh_apply_T_backward(const hh_desc *d, const void *U, int64_t ldu,
+                              const void *X, int64_t ldx, const void *dY,
+                              int64_t lddy, void *dX, int64_t lddx, void *dU,
+                              int64_t lddu, void *ws, size_t ws_bytes,
+                              hipStream_t stream);
+
+/* Gradients of L for Y = Q diag(lam) Q^T X: dX = S dY (S symmetric),
+ * dlam_i = sum_j (Q^T dY)_ij (Q^T X)_ij, dU as above.  All outputs nullable. */
+HH_API hh_status hh_sym_apply_backward(const hh_desc *d, const void *U, int64_t ldu,
+                                const void *lam, const void *X, int64_t ldx,
+                                const void *dY, int64_t lddy, void *dX,
+                                int64_t lddx, void *dU, int64_t lddu, void *dlam,
+                                void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Gradients of L for dist = hh_mahalanobis(...), with ddist[j] = dL/ddist_j
+ * (param_dtype, N long).  dXa = -dXb = Q (2 ddist_j lam .* z_j) with
+ * z_j = Q^T (xa_j - xb_j); dlam_i = sum_j ddist_j z_ij^2; dU as above.
+ * dXa and dXb share lddx.  All outputs nullable. */
+HH_API hh_status hh_mahalanobis_backward(const hh_desc *d, const void *U, int64_t ldu,
+                                  const void *lam, const void *Xa, int64_t lda,
+                                  const void *Xb, int64_t ldb, const void *ddist,
+                                  void *dXa, void *dXb, int64_t lddx, void *dU,
+                                  int64_t lddu, void *dlam, void *ws,
+                                  size_t ws_bytes, hipStream_t stream);
+
+/* Static text for a status code. */
+HH_API const char *hh_status_string(hh_status s);
+
+/* Detail of the last failing call on this thread ("" if none). */
+HH_API const char *hh_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+HH_API int hh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HH_H_ */

@@ -1,0 +1,393 @@
+// C ABI of libhh.so: argument validation, workspace layout and dispatch.
+// Every entry point validates on the host, enqueues on the caller's stream and
+// returns; nothing here allocates device memory or synchronises.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "hh_internal.h"
+#include "hh_wy.h"
+#include "hh_bwd.h"
+
+namespace hh {
+
+static thread_local std::string g_last_error;
+
+hh_status set_error(hh_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+#define fail set_error
+
+static hh_status hip_fail(hipError_t e, const char *what) {
+    return fail(HH_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int device_cu_count() {
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cache[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            v <= 0)
+            v = 256;
+        cache[dev] = v;
+    }
+    return cache[dev];
+}
+
+static size_t dtype_size(hh_dtype t) {
+    switch (t) {
+    case HH_F64: return 8;
+    case HH_F32: return 4;
+    case HH_BF16:
+    case HH_F16: return 2;
+    }
+    return 0;
+}
+
+static bool valid_dtype(hh_dtype t) { return t == HH_F64 || t == HH_F32 || t == HH_BF16 || t == HH_F16; }
+
+// ---------------------------------------------------------------------------
+// Descriptor checks shared by every entry point.
+enum class Algo { Fused, WY };
+
+static hh_status check_desc(const hh_desc *d, Algo *algo) {
+    if (!d) return fail(HH_ERR_INVALID_ARG, "descriptor is null");
+    if (d->n < 1) return fail(HH_ERR_INVALID_ARG, "n = %lld must be >= 1", (long long)d->n);
+    if (d->h < 0) return fail(HH_ERR_INVALID_ARG, "h = %lld must be >= 0", (long long)d->h);
+    if (d->N < 0) return fail(HH_ERR_INVALID_ARG, "N = %lld must be >= 0", (long long)d->N);
+    if (d->n > (int64_t)1 << 30 || d->h > (int64_t)1 << 30)
+        return fail(HH_ERR_UNSUPPORTED, "n and h must be < 2^30");
+    if (!valid_dtype(d->param_dtype) || !valid_dtype(d->io_dtype) || !valid_dtype(d->compute_dtype))
+        return fail(HH_ERR_INVALID_ARG, "unknown dtype code");
+    hh_algo a = d->algo;
+    if (a == HH_ALGO_AUTO)
+        a = (d->compute_dtype == HH_F64 || d->compute_dtype == HH_F32) ? HH_ALGO_FUSED : HH_ALGO_WY;
+    if (a == HH_ALGO_FUSED) {
+        if (!(d->compute_dtype == HH_F64 || d->compute_dtype == HH_F32) ||
+            d->param_dtype != d->compute_dtype || d->io_dtype != d->compute_dtype)
+            return fail(HH_ERR_UNSUPPORTED,
+                        "FUSED needs param = io = compute in {F64, F32}");
+        *algo = Algo::Fused;
+        return HH_OK;
+    }
+    if (a == HH_ALGO_WY) {
+        if (!(d->compute_dtype == HH_BF16 || d->compute_dtype == HH_F16) ||
+            d->param_dtype != HH_F32 ||
+            !(d->io_dtype == d->compute_dtype || d->io_dtype == HH_F32))
+            return fail(HH_ERR_UNSUPPORTED,
+                        "WY needs compute in {BF16, F16}, param F32, io = compute or F32");
+        *algo = Algo::WY;
+        return HH_OK;
+    }
+    return fail(HH_ERR_INVALID_ARG, "unknown algo code");
+}
+
+static hh_status check_ld(const char *name, int64_t ld, int64_t n) {
+    if (ld < n) return fail(HH_ERR_INVALID_ARG, "%s = %lld must be >= n = %lld", name, (long long)ld, (long long)n);
+    return HH_OK;
+}
+
+static hh_status check_ptr(const char *name, const void *p) {
+    if (!p) return fail(HH_ERR_INVALID_ARG, "%s must not be null", name);
+    return HH_OK;
+}
+
+#define HH_TRY(expr)                  \
+    do {                              \
+        hh_status _s = (expr);        \
+        if (_s != HH_OK) return _s;   \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Workspace layout of the fused path.
+struct FusedWs {
+    size_t ut, tau, lam, uh64, nrm64, bwd, total;
+};
+
+static bool is_bwd(hh_op op) { return op >= HH_OP_APPLY_BWD; }
+static bool uses_lam(hh_op op) {
+    return op == HH_OP_SYM || op == HH_OP_MAHAL || op == HH_OP_SYM_BWD || op == HH_OP_MAHAL_BWD;
+}
+
+static FusedWs fused_ws(hh_op op, const FusedPlan &p) {
+    const size_t es = dtype_size(p.t);
+    const size_t h = (size_t)p.h, npad = (size_t)p.s.npad;
+    FusedWs w{};
+    size_t off = 0;
+    w.ut = off;   off += align256(h * npad * es);
+    w.tau = off;  off += align256(std::max<size_t>(h, 1) * es);
+    w.lam = off;  off += uses_lam(op) ? align256(npad * es) : 0;
+    w.uh64 = off; off += is_bwd(op) ? align256(h * (size_t)p.n * 8) : 0;
+    w.nrm64 = off; off += is_bwd(op) ? align256(std::max<size_t>(h, 1) * 8) : 0;
+    w.bwd = off;  off += is_bwd(op) ? fused_bwd_ws_bytes(op, p) : 0;
+    w.total = off;
+    return w;
+}
+
+static hh_status make_fused_plan(const hh_desc *d, FusedPlan *p) {
+    if (!fused_plan(d->compute_dtype, d->n, d->h, d->N, p))
+        return fail(HH_ERR_UNSUPPORTED,
+                    "fused path supports n <= %d for this dtype (n = %lld)",
+                    d->compute_dtype == HH_F64 ? 4096 : 8192, (long long)d->n);
+    return HH_OK;
+}
+
+static hh_status make_fused_bwd_plan(const hh_desc *d, FusedPlan *p) {
+    if (!fused_bwd_plan(d->compute_dtype, d->n, d->h, d->N, p))
+        return fail(HH_ERR_UNSUPPORTED,
+                    "fused backward supports n <= %d for this dtype (n = %lld)",
+                    d->compute_dtype == HH_F64 ? 2048 : 4096, (long long)d->n);
+    return HH_OK;
+}
+
+static int aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+// ---------------------------------------------------------------------------
+// Forward entry (all four ops).
+static hh_status forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
+                         const void *lam, const void *X, int64_t ldx, const void *Xb,
+                         int64_t ldb, void *Y, int64_t ldy, void *ws, size_t ws_bytes,
+                         hipStream_t st) {
+    Algo algo;
+    HH_TRY(check_desc(d, &algo));
+    const int64_t n = d->n, h = d->h, N = d->N;
+    HH_TRY(check_ld("ldu", ldu, h > 0 ? n : 0));
+    HH_TRY(check_ld(op == HH_OP_MAHAL ? "lda" : "ldx", ldx, n));
+    if (op == HH_OP_MAHAL) HH_TRY(check_ld("ldb", ldb, n));
+    else HH_TRY(check_ld("ldy", ldy, n));
+    if (algo == Algo::WY) return wy_forward(op, d, U, ldu, lam, X, ldx, Xb, ldb, Y, ldy, ws, ws_bytes, st);
+
+    FusedPlan p;
+    HH_TRY(make_fused_plan(d, &p));
+    const FusedWs w = fused_ws(op, p);
+    if (N == 0) return HH_OK;
+    if (h > 0) HH_TRY(check_ptr("U", U));
+    HH_TRY(check_ptr(op == HH_OP_MAHAL ? "Xa" : "X", X));
+    HH_TRY(check_ptr(op == HH_OP_MAHAL ? "dist" : "Y", Y));
+    if (op == HH_OP_MAHAL) HH_TRY(check_ptr("Xb", Xb));
+    if (uses_lam(op)) HH_TRY(check_ptr("lam", lam));
+    if (op != HH_OP_MAHAL && Y == X && ldy != ldx)
+        return fail(HH_ERR_INVALID_ARG, "in-place call needs ldy == ldx");
+    if (w.total > 0) HH_TRY(check_ptr("ws", ws));
+    if (ws_bytes < w.total)
+        return fail(HH_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", w.total, ws_bytes);
+
+    char *base = static_cast<char *>(ws);
+    hipError_t e = launch_setup_fused(p.t, U, ldu, uses_lam(op) ? lam : nullptr, n, h, p.s.npad,
+                                      base + w.ut, base + w.tau,
+                                      uses_lam(op) ? base + w.lam : nullptr, nullptr, nullptr, st);
+    if (e != hipSuccess) return hip_fail(e, "setup launch");
+
+    const size_t es = dtype_size(p.t);
+    const int wvec = 16 / (int)es;
+    FusedFwdArgs a{};
+    a.X = X;
+    a.ldx = ldx;
+    a.Xb = Xb;
+    a.ldb = ldb;
+    a.Y = Y;
+    a.ldy = ldy;
+    a.ut = base + w.ut;
+    a.tau = base + w.tau;
+    a.lam = base + w.lam;
+    a.n = (int)n;
+    a.h = (int)h;
+    a.npad = p.s.npad;
+    a.hc = p.hc;
+    a.N = N;
+    bool vec = (n % wvec == 0) && aligned16(X) && (ldx % wvec == 0);
+    if (op == HH_OP_MAHAL) vec = vec && aligned16(Xb) && (ldb % wvec == 0);
+    else vec = vec && aligned16(Y) && (ldy % wvec == 0);
+    a.vec_ok = vec ? 1 : 0;
+    FusedOp fop = op == HH_OP_APPLY ? F_APPLY : op == HH_OP_APPLY_T ? F_APPLY_T
+                : op == HH_OP_SYM ? F_SYM : F_MAHAL;
+    e = launch_fused_fwd(p, fop, a, st);
+    if (e != hipSuccess) return hip_fail(e, "fused kernel launch");
+    return HH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Backward entry (all four ops).
+static hh_status backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
+                          const void *lam, const void *X, int64_t ldx, const void *Xb,
+                          int64_t ldb, const void *G, int64_t ldg, void *dX, void *dXb,
+                          int64_t lddx, void *dU, int64_t lddu, void *dlam, void *ws,
+                          size_t ws_bytes, hipStream_t st) {
+    Algo algo;
+    HH_TRY(check_desc(d, &algo));
+    const int64_t n = d->n, h = d->h, N = d->N;
+    HH_TRY(check_ld("ldu", ldu, h > 0 ? n : 0));
+    HH_TRY(check_ld(op == HH_OP_MAHAL_BWD ? "lda" : "ldx", ldx, n));
+    if (op == HH_OP_MAHAL_BWD) HH_TRY(check_ld("ldb", ldb, n));
+    else HH_TRY(check_ld("lddy", ldg, n));
+    if (dX || dXb) HH_TRY(check_ld("lddx", lddx, n));
+    if (dU && h > 0) HH_TRY(check_ld("lddu", lddu, n));
+    if (algo == Algo::WY)
+        return wy_backward(op, d, U, ldu, lam, X, ldx, Xb, ldb, G, ldg, dX, dXb, lddx, dU, lddu,
+                           dlam, ws, ws_bytes, st);
+
+    FusedPlan p;
+    HH_TRY(make_fused_bwd_plan(d, &p));
+    if (!fused_bwd_supported(op, p))
+        return fail(HH_ERR_UNSUPPORTED,
+                    "fused backward needs all h reflectors in LDS (n = %lld, h = %lld)",
+                    (long long)n, (long long)h);
+    const FusedWs w = fused_ws(op, p);
+    if (h > 0) HH_TRY(check_ptr("U", U));
+    if (N > 0) {
+        HH_TRY(check_ptr(op == HH_OP_MAHAL_BWD ? "Xa" : "X", X));
+        HH_TRY(check_ptr(op == HH_OP_MAHAL_BWD ? "ddist" : "dY", G));
+        if (op == HH_OP_MAHAL_BWD) HH_TRY(check_ptr("Xb", Xb));
+    }
+    if (uses_lam(op)) HH_TRY(check_ptr("lam", lam));
+    if (w.total > 0) HH_TRY(check_ptr("ws", ws));
+    if (ws_bytes < w.total)
+        return fail(HH_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", w.total, ws_bytes);
+
+    char *base = static_cast<char *>(ws);
+    hipError_t e = launch_setup_fused(p.t, U, ldu, uses_lam(op) ? lam : nullptr, n, h, p.s.npad,
+                                      base + w.ut, base + w.tau,
+                                      uses_lam(op) ? base + w.lam : nullptr,
+                                      reinterpret_cast<double *>(base + w.uh64),
+                                      reinterpret_cast<double *>(base + w.nrm64), st);
+    if (e != hipSuccess) return hip_fail(e, "setup launch");
+    const size_t es = dtype_size(p.t);
+    const int wvec = 16 / (int)es;
+    FusedBwdArgs a{};
+    a.X = X;
+    a.ldx = ldx;
+    a.Xb = Xb;
+    a.ldb = ldb;
+    a.G = G;
+    a.ldg = ldg;
+    a.dX = dX;
+    a.dXb = dXb;
+    a.lddx = lddx;
+    a.ut = base + w.ut;
+    a.tau = base + w.tau;
+    a.lam = base + w.lam;
+    a.uh64 = reinterpret_cast<const double *>(base + w.uh64);
+    a.nrm64 = reinterpret_cast<const double *>(base + w.nrm64);
+    a.dU = dU;
+    a.lddu = lddu;
+    a.dlam = dlam;
+    a.scratch = base + w.bwd;
+    a.n = (int)n;
+    a.h = (int)h;
+    a.npad = p.s.npad;
+    a.N = N;
+    bool vec = (n % wvec == 0) && aligned16(X) && (ldx % wvec == 0);
+    if (op == HH_OP_MAHAL_BWD) vec = vec && aligned16(Xb) && (ldb % wvec == 0);
+    else vec = vec && aligned16(G) && (ldg % wvec == 0);
+    if (dX) vec = vec && aligned16(dX) && (lddx % wvec == 0);
+    if (dXb) vec = vec && aligned16(dXb) && (lddx % wvec == 0);
+    a.vec_ok = vec ? 1 : 0;
+    e = launch_fused_bwd(p, op, a, st);
+    if (e != hipSuccess) return hip_fail(e, "fused backward launch");
+    return HH_OK;
+}
+
+}  // namespace hh
+
+using namespace hh;
+
+extern "C" {
+
+hh_status hh_workspace_size(hh_op op, const hh_desc *d, size_t *bytes) {
+    if (!bytes) return fail(HH_ERR_INVALID_ARG, "bytes must not be null");
+    if ((int)op < HH_OP_APPLY || (int)op > HH_OP_MAHAL_BWD) return fail(HH_ERR_INVALID_ARG, "unknown op");
+    Algo algo;
+    HH_TRY(check_desc(d, &algo));
+    if (algo == Algo::WY) return wy_workspace_size(op, d, bytes);
+    FusedPlan p;
+    if (is_bwd(op)) HH_TRY(make_fused_bwd_plan(d, &p));
+    else HH_TRY(make_fused_plan(d, &p));
+    if (is_bwd(op) && !fused_bwd_supported(op, p))
+        return fail(HH_ERR_UNSUPPORTED, "fused backward needs all h reflectors in LDS");
+    *bytes = fused_ws(op, p).total;
+    return HH_OK;
+}
+
+hh_status hh_apply(const hh_desc *d, const void *U, int64_t ldu, const void *X, int64_t ldx,
+                   void *Y, int64_t ldy, void *ws, size_t ws_bytes, hipStream_t stream) {
+    return forward(HH_OP_APPLY, d, U, ldu, nullptr, X, ldx, nullptr, 0, Y, ldy, ws, ws_bytes,
+                   stream);
+}
+
+hh_status hh_apply_T(const hh_desc *d, const void *U, int64_t ldu, const void *X, int64_t ldx,
+                     void *Y, int64_t ldy, void *ws, size_t ws_bytes, hipStream_t stream) {
+    return forward(HH_OP_APPLY_T, d, U, ldu, nullptr, X, ldx, nullptr, 0, Y, ldy, ws, ws_bytes,
+                   stream);
+}
+
+hh_status hh_sym_apply(const hh_desc *d, const void *U, int64_t ldu, const void *lam,
+                       const void *X, int64_t ldx, void *Y, int64_t ldy, void *ws,
+                       size_t ws_bytes, hipStream_t stream) {
+    return forward(HH_OP_SYM, d, U, ldu, lam, X, ldx, nullptr, 0, Y, ldy, ws, ws_bytes, stream);
+}
+
+hh_status hh_mahalanobis(const hh_desc *d, const void *U, int64_t ldu, const void *lam,
+                         const void *Xa, int64_t lda, const void *Xb, int64_t ldb, void *dist,
+                         void *ws, size_t ws_bytes, hipStream_t stream) {
+    return forward(HH_OP_MAHAL, d, U, ldu, lam, Xa, lda, Xb, ldb, dist, 0, ws, ws_bytes, stream);
+}
+
+hh_status hh_apply_backward(const hh_desc *d, const void *U, int64_t ldu, const void *X,
+                            int64_t ldx, const void *dY, int64_t lddy, void *dX, int64_t lddx,
+                            void *dU, int64_t lddu, void *ws, size_t ws_bytes,
+                            hipStream_t stream) {
+    return backward(HH_OP_APPLY_BWD, d, U, ldu, nullptr, X, ldx, nullptr, 0, dY, lddy, dX,
+                    nullptr, lddx, dU, lddu, nullptr, ws, ws_bytes, stream);
+}
+
+hh_status hh_apply_T_backward(const hh_desc *d, const void *U, int64_t ldu, const void *X,
+                              int64_t ldx, const void *dY, int64_t lddy, void *dX,
+                              int64_t lddx, void *dU, int64_t lddu, void *ws, size_t ws_bytes,
+                              hipStream_t stream) {
+    return backward(HH_OP_APPLY_T_BWD, d, U, ldu, nullptr, X, ldx, nullptr, 0, dY, lddy, dX,
+                    nullptr, lddx, dU, lddu, nullptr, ws, ws_bytes, stream);
+}
+
+hh_status hh_sym_apply_backward(const hh_desc *d, const void *U, int64_t ldu, const void *lam,
+                                const void *X, int64_t ldx, const void *dY, int64_t lddy,
+                                void *dX, int64_t lddx, void *dU, int64_t lddu, void *dlam,
+                                void *ws, size_t ws_bytes, hipStream_t stream) {
+    return backward(HH_OP_SYM_BWD, d, U, ldu, lam, X, ldx, nullptr, 0, dY, lddy, dX, nullptr,
+                    lddx, dU, lddu, dlam, ws, ws_bytes, stream);
+}
+
+hh_status hh_mahalanobis_backward(const hh_desc *d, const void *U, int64_t ldu, const void *lam,
+                                  const void *Xa, int64_t lda, const void *Xb, int64_t ldb,
+                                  const void *ddist, void *dXa, void *dXb, int64_t lddx,
+                                  void *dU, int64_t lddu, void *dlam, void *ws,
+                                  size_t ws_bytes, hipStream_t stream) {
+    return backward(HH_OP_MAHAL_BWD, d, U, ldu, lam, Xa, lda, Xb, ldb, ddist, 0, dXa, dXb, lddx,
+                    dU, lddu, dlam, ws, ws_bytes, stream);
+}
+
+const char *hh_status_string(hh_status s) {
+    switch (s) {
+    case HH_OK: return "HH_OK";
+    case HH_ERR_INVALID_ARG: return "HH_ERR_INVALID_ARG: invalid argument";
+    case HH_ERR_UNSUPPORTED: return "HH_ERR_UNSUPPORTED: unsupported combination";
+    case HH_ERR_WORKSPACE: return "HH_ERR_WORKSPACE: workspace too small";
+    case HH_ERR_HIP: return "HH_ERR_HIP: HIP runtime error";
+    }
+    return "unknown hh_status";
+}
+
+const char *hh_last_error(void) { return g_last_error.c_str(); }
+
+int hh_version(void) { return 100; }
+
+}  // extern "C"

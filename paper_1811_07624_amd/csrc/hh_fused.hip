@@ -1,0 +1,289 @@
+// Fused sequential-reflector kernels (forward): Q X, Q^T X, Q diag(lam) Q^T X
+// and the Mahalanobis distance, in FP32 or FP64.
+//
+// Each vector is applied the reflectors one after another (paper Sec. II-A:
+// a dot product and an update per reflector, 4n operations; Sec. III-A:
+// (8h+1)n for the symmetric form).  The vector never leaves the registers
+// between its single HBM read and its single HBM write.
+//
+// Mapping: LPV lanes (16 or 64) own one vector; lane c holds NC 16-byte chunks
+// at element offsets i*LPV*W + c*W (W = 4 floats or 2 doubles), so every load
+// and store instruction moves LPV*16 contiguous bytes per vector.  A dot
+// product is a per-lane partial sum followed by a DPP reduction across the
+// LPV lanes (no LDS round trip).  Reflectors (and the spectrum) are staged in
+// LDS, all at once when they fit, otherwise in chunks of hc reflectors that
+// every wave of the block walks through in lockstep.
+#include <algorithm>
+
+#include "hh_internal.h"
+
+namespace hh {
+namespace {
+
+constexpr int kWPB = 4;          // waves per block
+constexpr int kThreads = kWPB * kWave;
+constexpr size_t kLdsBudget = 64 * 1024;
+
+template <typename T, int LPV, int NC, int OP>
+__global__ __launch_bounds__(kThreads) void k_fused_fwd(FusedFwdArgs a) {
+    using VT = typename V16<T>::type;
+    constexpr int W = V16<T>::W;
+    constexpr int E = NC * W;      // elements per lane
+    constexpr int VPW = kWave / LPV;
+    constexpr int STR = LPV * W;   // element stride between a lane's chunks
+    extern __shared__ __align__(16) unsigned char smem[];
+
+    const int n = a.n, h = a.h, npad = a.npad, hc = a.hc;
+    T *sU = reinterpret_cast<T *>(smem);
+    T *sLam = sU + (size_t)hc * npad;
+    const T *gU = static_cast<const T *>(a.ut);
+    const T *gTau = static_cast<const T *>(a.tau);
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
+    const int c = lane % LPV;
+    const int row = lane / LPV;
+
+    if constexpr (OP == F_SYM || OP == F_MAHAL) {
+        const VT *src = static_cast<const VT *>(a.lam);
+        for (int i = tid; i < npad / W; i += kThreads) reinterpret_cast<VT *>(sLam)[i] = src[i];
+    }
+    __syncthreads();
+
+    const int nchunks = h > 0 ? (h + hc - 1) / hc : 0;
+    int loaded = -1;  // block-uniform
+    auto load_chunk = [&](int q) {
+        if (q == loaded) return;
+        __syncthreads();
+        const int k0 = q * hc;
+        const int cnt = min(hc, h - k0);
+        const VT *src = reinterpret_cast<const VT *>(gU + (size_t)k0 * npad);
+        VT *dst = reinterpret_cast<VT *>(sU);
+        const int total = cnt * (npad / W);
+        for (int i = tid; i < total; i += kThreads) dst[i] = src[i];
+        __syncthreads();
+        loaded = q;
+    };
+    if (nchunks == 1) load_chunk(0);
+
+    // One reflection of the lane's slice of the vector by reflector k.
+    auto reflect = [&](int k, T(&x)[E]) {
+        const T *u = sU + (size_t)(k - loaded * hc) * npad + c * W;
+        T part[W];
+#pragma unroll
+        for (int v = 0; v < W; ++v) part[v] = (T)0;
+        VT uv[NC];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            uv[i] = *reinterpret_cast<const VT *>(u + i * STR);
+#pragma unroll
+            for (int v = 0; v < W; ++v) part[v] = fmat(uv[i][v], x[i * W + v], part[v]);
+        }
+        T p = part[0];
+#pragma unroll
+        for (int v = 1; v < W; ++v) p += part[v];
+        p = group_sum<LPV>(p);
+        const T coef = -p * gTau[k];
+#pragma unroll
+        for (int i = 0; i < NC; ++i)
+#pragma unroll
+            for (int v = 0; v < W; ++v) x[i * W + v] = fmat(coef, uv[i][v], x[i * W + v]);
+    };
+    auto run_up = [&](T(&x)[E]) {  // k = 0 .. h-1  (Q^T: H_1 first)
+#pragma unroll 1
+        for (int q = 0; q < nchunks; ++q) {
+            load_chunk(q);
+            const int kend = min(h, (q + 1) * hc);
+#pragma unroll 1
+            for (int k = q * hc; k < kend; ++k) reflect(k, x);
+        }
+    };
+    auto run_down = [&](T(&x)[E]) {  // k = h-1 .. 0  (Q: H_h first)
+#pragma unroll 1
+        for (int q = nchunks - 1; q >= 0; --q) {
+            load_chunk(q);
+            const int kend = min(h, (q + 1) * hc);
+#pragma unroll 1
+            for (int k = kend - 1; k >= q * hc; --k) reflect(k, x);
+        }
+    };
+    auto load_vec = [&](T(&x)[E], const T *base, int64_t ld, int64_t j, bool valid) {
+        if (a.vec_ok) {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                const int e0 = i * STR + c * W;
+                VT v = {};
+                if (valid && e0 < n) v = *reinterpret_cast<const VT *>(base + j * ld + e0);
+#pragma unroll
+                for (int q = 0; q < W; ++q) x[i * W + q] = v[q];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const int e = i * STR + c * W + q;
+                    x[i * W + q] = (valid && e < n) ? base[j * ld + e] : (T)0;
+                }
+        }
+    };
+    auto store_vec = [&](const T(&x)[E], T *base, int64_t ld, int64_t j, bool valid) {
+        if (!valid) return;
+        if (a.vec_ok) {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                const int e0 = i * STR + c * W;
+                if (e0 < n) {
+                    VT v;
+#pragma unroll
+                    for (int q = 0; q < W; ++q) v[q] = x[i * W + q];
+                    *reinterpret_cast<VT *>(base + j * ld + e0) = v;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const int e = i * STR + c * W + q;
+                    if (e < n) base[j * ld + e] = x[i * W + q];
+                }
+        }
+    };
+
+    const int64_t vpb = (int64_t)kWPB * VPW;
+    for (int64_t b0 = (int64_t)blockIdx.x * vpb; b0 < a.N; b0 += (int64_t)gridDim.x * vpb) {
+        const int64_t j = b0 + wave * VPW + row;
+        const bool valid = j < a.N;
+        T x[E];
+        load_vec(x, static_cast<const T *>(a.X), a.ldx, j, valid);
+        if constexpr (OP == F_MAHAL) {
+            T xb[E];
+            load_vec(xb, static_cast<const T *>(a.Xb), a.ldb, j, valid);
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] -= xb[e];
+        }
+        if constexpr (OP == F_APPLY) run_down(x);
+        if constexpr (OP == F_APPLY_T || OP == F_SYM || OP == F_MAHAL) run_up(x);
+        if constexpr (OP == F_SYM) {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                VT l = *reinterpret_cast<const VT *>(sLam + i * STR + c * W);
+#pragma unroll
+                for (int q = 0; q < W; ++q) x[i * W + q] *= l[q];
+            }
+            run_down(x);
+        }
+        if constexpr (OP == F_MAHAL) {
+            T part = (T)0;
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                VT l = *reinterpret_cast<const VT *>(sLam + i * STR + c * W);
+#pragma unroll
+                for (int q = 0; q < W; ++q) part = fmat(l[q] * x[i * W + q], x[i * W + q], part);
+            }
+            part = group_sum<LPV>(part);
+            if (valid && c == 0) static_cast<T *>(a.Y)[j] = part;
+        } else {
+            store_vec(x, static_cast<T *>(a.Y), a.ldy, j, valid);
+        }
+    }
+}
+
+template <typename T, int LPV, int NC>
+hipError_t launch_op(FusedOp op, const FusedPlan &p, const FusedFwdArgs &a, dim3 grid,
+                     hipStream_t st) {
+    switch (op) {
+    case F_APPLY:
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_APPLY>), grid, dim3(kThreads), p.lds_bytes,
+                           st, a);
+        break;
+    case F_APPLY_T:
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_APPLY_T>), grid, dim3(kThreads),
+                           p.lds_bytes, st, a);
+        break;
+    case F_SYM:
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_SYM>), grid, dim3(kThreads), p.lds_bytes, st,
+                           a);
+        break;
+    case F_MAHAL:
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_MAHAL>), grid, dim3(kThreads), p.lds_bytes,
+                           st, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch(FusedOp op, const FusedPlan &p, const FusedFwdArgs &a, dim3 grid,
+                    hipStream_t st) {
+    const int lpv = p.s.lpv, nc = p.s.nc;
+    if (lpv == 16) {
+        switch (nc) {
+        case 1: return launch_op<T, 16, 1>(op, p, a, grid, st);
+        case 2: return launch_op<T, 16, 2>(op, p, a, grid, st);
+        case 4: return launch_op<T, 16, 4>(op, p, a, grid, st);
+        case 8: return launch_op<T, 16, 8>(op, p, a, grid, st);
+        case 16: return launch_op<T, 16, 16>(op, p, a, grid, st);
+        }
+    } else if (lpv == 64) {
+        switch (nc) {
+        case 8: return launch_op<T, 64, 8>(op, p, a, grid, st);
+        case 16: return launch_op<T, 64, 16>(op, p, a, grid, st);
+        case 32: return launch_op<T, 64, 32>(op, p, a, grid, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+int next_pow2(int64_t v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+bool fused_shape(hh_dtype t, int64_t n, FusedShape *s) {
+    const int W = (t == HH_F64) ? 2 : 4;
+    if (n <= 16 * W * 16) {
+        s->lpv = 16;
+        s->nc = next_pow2((n + 16 * W - 1) / (16 * W));
+    } else if (n <= 64 * W * 32) {
+        s->lpv = 64;
+        s->nc = std::max(8, next_pow2((n + 64 * W - 1) / (64 * W)));
+    } else {
+        return false;
+    }
+    s->npad = s->nc * s->lpv * W;
+    return true;
+}
+
+bool fused_plan(hh_dtype t, int64_t n, int64_t h, int64_t N, FusedPlan *p) {
+    p->t = t;
+    p->n = n;
+    p->h = h;
+    p->N = N;
+    if (!fused_shape(t, n, &p->s)) return false;
+    const size_t es = (t == HH_F64) ? 8 : 4;
+    const size_t vec_bytes = (size_t)p->s.npad * es;
+    const size_t fixed = vec_bytes;  // spectrum
+    if (fixed + vec_bytes > kLdsBudget) return false;
+    const int64_t fit = (int64_t)((kLdsBudget - fixed) / vec_bytes);
+    p->hc = (int)std::max<int64_t>(1, std::min<int64_t>(h, fit));
+    p->lds_bytes = fixed + (size_t)p->hc * vec_bytes;
+    return true;
+}
+
+hipError_t launch_fused_fwd(const FusedPlan &p, FusedOp op, const FusedFwdArgs &a,
+                            hipStream_t st) {
+    const int vpb = kWPB * (kWave / p.s.lpv);
+    const int64_t need = (p.N + vpb - 1) / vpb;
+    const int64_t cap = (int64_t)device_cu_count() * 8;
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min(need, cap)));
+    if (p.t == HH_F32) return dispatch<float>(op, p, a, grid, st);
+    return dispatch<double>(op, p, a, grid, st);
+}
+
+}  // namespace hh

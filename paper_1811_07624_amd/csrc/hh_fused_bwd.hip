@@ -1,0 +1,455 @@
+// Fused backward kernels for Q X, Q^T X, Q diag(lam) Q^T X and the
+// Mahalanobis distance, in FP32 or FP64.
+//
+// The paper never differentiates the application of its factorisation; the
+// gradients here are the chain rule of the reflector steps it defines
+// (Sec. II-A, eq. 2).  For one step s_r = s_{r-1} - tau (u^T s_{r-1}) u with
+// upstream g_r = dL/ds_r:
+//     dL/ds_{r-1} = g_r - tau (u^T g_r) u          (H is symmetric)
+//     dL/du      += -tau [ (u^T s_{r-1}) g_r + (u^T g_r) s_{r-1} ]
+// Intermediate vectors are not stored: the forward sweep keeps only the h dot
+// products a_r = u^T s_{r-1} (in LDS), and the reverse sweep rebuilds
+// s_{r-1} = s_r + tau a_r u, which undoes the forward update exactly up to one
+// rounding because H is its own inverse.
+//
+// One wave owns one vector (64 lanes x NC 16-byte chunks).  Reflectors are
+// read from LDS when all h fit, otherwise straight from the workspace (L2).
+// dL/du for HB
+// reflectors at a time stays in registers across all the vectors a block
+// processes; larger h takes several passes.  Each block writes its partial
+// sums; a second kernel adds the block partials in a fixed order in FP64
+// (deterministic for a given grid), scales by -tau_k and applies the chain
+// rule of the normalisation uh = u/||u||: dU = (I - uh uh^T) dL/duh / ||u||.
+#include <algorithm>
+
+#include "hh_bwd.h"
+
+namespace hh {
+namespace {
+
+constexpr int kWPB = 4;
+constexpr int kThreads = kWPB * kWave;
+constexpr size_t kLdsBudget = 64 * 1024;
+
+enum BwdOp { B_APPLY = 0, B_APPLY_T = 1, B_SYM = 2, B_MAHAL = 3 };
+
+template <typename T, int NC> constexpr int hb_for() {
+    constexpr int regs_per_elem = sizeof(T) / 4;
+    constexpr int E = NC * V16<T>::W;
+    constexpr int hb = 128 / (E * regs_per_elem);
+    return hb < 1 ? 1 : (hb > 16 ? 16 : hb);
+}
+
+template <typename T, int NC, int OP, bool UL>
+__global__ __launch_bounds__(kThreads) void k_fused_bwd(FusedBwdArgs a, int k0, int kcnt,
+                                                       int write_dx, int do_lam, int nblocks) {
+    using VT = typename V16<T>::type;
+    constexpr int W = V16<T>::W;
+    constexpr int E = NC * W;
+    constexpr int STR = kWave * W;
+    constexpr int HB = hb_for<T, NC>();
+    extern __shared__ __align__(16) unsigned char smem[];
+
+    const int n = a.n, h = a.h, npad = a.npad;
+    const int R = (OP == B_SYM) ? 2 * h : h;
+    // LDS: [reflectors (UL only)] [spectrum] [combine buffer] [saved dots]
+    T *sU = reinterpret_cast<T *>(smem);
+    T *sLam = sU + (UL ? (size_t)h * npad : 0);
+    T *sComb = sLam + npad;
+    T *sAl = sComb + npad;
+    const T *gTau = static_cast<const T *>(a.tau);
+    const T *uBase = UL ? sU : static_cast<const T *>(a.ut);
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
+    {
+        if constexpr (UL) {
+            const VT *src = static_cast<const VT *>(a.ut);
+            VT *dst = reinterpret_cast<VT *>(sU);
+            const int total = h * (npad / W);
+            for (int i = tid; i < total; i += kThreads) dst[i] = src[i];
+        }
+        if constexpr (OP == B_SYM || OP == B_MAHAL) {
+            const VT *ls = static_cast<const VT *>(a.lam);
+            for (int i = tid; i < npad / W; i += kThreads) reinterpret_cast<VT *>(sLam)[i] = ls[i];
+        }
+    }
+    __syncthreads();
+    T *myAl = sAl + wave * (R > 0 ? R : 1);
+
+    T acc[HB][E];
+    T lacc[E];
+#pragma unroll
+    for (int b = 0; b < HB; ++b)
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[b][e] = (T)0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) lacc[e] = (T)0;
+
+    auto load_u = [&](int k, VT(&uv)[NC]) {
+        const T *u = uBase + (size_t)k * npad + lane * W;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) uv[i] = *reinterpret_cast<const VT *>(u + i * STR);
+    };
+    auto dot = [&](const VT(&uv)[NC], const T(&v)[E]) {
+        T part[W];
+#pragma unroll
+        for (int q = 0; q < W; ++q) part[q] = (T)0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i)
+#pragma unroll
+            for (int q = 0; q < W; ++q) part[q] = fmat(uv[i][q], v[i * W + q], part[q]);
+        T p = part[0];
+#pragma unroll
+        for (int q = 1; q < W; ++q) p += part[q];
+        return group_sum<64>(p);
+    };
+    auto axpy = [&](T coef, const VT(&uv)[NC], T(&v)[E]) {
+#pragma unroll
+        for (int i = 0; i < NC; ++i)
+#pragma unroll
+            for (int q = 0; q < W; ++q) v[i * W + q] = fmat(coef, uv[i][q], v[i * W + q]);
+    };
+    // forward sweep over one chain; up: k = r, down: k = h-1-r.  Stores a_r.
+    auto fwd_chain = [&](bool up, T(&s)[E], int abase) {
+#pragma unroll 1
+        for (int r = 0; r < h; ++r) {
+            const int k = up ? r : h - 1 - r;
+            VT uv[NC];
+            load_u(k, uv);
+            const T p = dot(uv, s);
+            if (lane == 0) myAl[abase + r] = p;
+            axpy(-p * gTau[k], uv, s);
+        }
+    };
+    // reverse sweep: rebuilds s_{r-1}, propagates g, accumulates dL/du.
+    auto rev_chain = [&](bool up, T(&s)[E], T(&g)[E], int abase) {
+#pragma unroll 1
+        for (int r = h - 1; r >= 0; --r) {
+            const int k = up ? r : h - 1 - r;
+            VT uv[NC];
+            load_u(k, uv);
+            const T beta = dot(uv, g);
+            const T p = myAl[abase + r];
+            const T t = gTau[k];
+            axpy(t * p, uv, s);  // s <- s_{r-1}
+            const int kb = k - k0;
+            if (kb >= 0 && kb < kcnt) {
+#pragma unroll
+                for (int b = 0; b < HB; ++b)
+                    if (b == kb) {
+#pragma unroll
+                        for (int e = 0; e < E; ++e)
+                            acc[b][e] = fmat(p, g[e], fmat(beta, s[e], acc[b][e]));
+                    }
+            }
+            axpy(-t * beta, uv, g);
+        }
+    };
+    auto load_vec = [&](T(&x)[E], const T *base, int64_t ld, int64_t j, bool valid) {
+        if (a.vec_ok) {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                const int e0 = i * STR + lane * W;
+                VT v = {};
+                if (valid && e0 < n) v = *reinterpret_cast<const VT *>(base + j * ld + e0);
+#pragma unroll
+                for (int q = 0; q < W; ++q) x[i * W + q] = v[q];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const int e = i * STR + lane * W + q;
+                    x[i * W + q] = (valid && e < n) ? base[j * ld + e] : (T)0;
+                }
+        }
+    };
+    auto store_vec = [&](const T(&x)[E], T sign, T *base, int64_t ld, int64_t j) {
+        if (a.vec_ok) {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                const int e0 = i * STR + lane * W;
+                if (e0 < n) {
+                    VT v;
+#pragma unroll
+                    for (int q = 0; q < W; ++q) v[q] = sign * x[i * W + q];
+                    *reinterpret_cast<VT *>(base + j * ld + e0) = v;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const int e = i * STR + lane * W + q;
+                    if (e < n) base[j * ld + e] = sign * x[i * W + q];
+                }
+        }
+    };
+    auto lam_chunk = [&](int i) { return *reinterpret_cast<const VT *>(sLam + i * STR + lane * W); };
+
+    for (int64_t b0 = (int64_t)blockIdx.x * kWPB; b0 < a.N; b0 += (int64_t)gridDim.x * kWPB) {
+        const int64_t j = b0 + wave;
+        const bool valid = j < a.N;
+        T s[E], g[E];
+        load_vec(s, static_cast<const T *>(a.X), a.ldx, j, valid);
+        if constexpr (OP == B_MAHAL) {
+            load_vec(g, static_cast<const T *>(a.Xb), a.ldb, j, valid);
+#pragma unroll
+            for (int e = 0; e < E; ++e) s[e] -= g[e];
+        }
+        if constexpr (OP == B_APPLY || OP == B_APPLY_T) {
+            constexpr bool up = (OP == B_APPLY_T);
+            fwd_chain(up, s, 0);
+            load_vec(g, static_cast<const T *>(a.G), a.ldg, j, valid);
+            rev_chain(up, s, g, 0);
+        } else if constexpr (OP == B_SYM) {
+            fwd_chain(true, s, 0);
+            T z[E];
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                const VT l = lam_chunk(i);
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    z[i * W + q] = s[i * W + q];
+                    s[i * W + q] *= l[q];
+                }
+            }
+            fwd_chain(false, s, h);
+            load_vec(g, static_cast<const T *>(a.G), a.ldg, j, valid);
+            rev_chain(false, s, g, h);  // g = Q^T dY
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                const VT l = lam_chunk(i);
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    lacc[i * W + q] = fmat(g[i * W + q], z[i * W + q], lacc[i * W + q]);
+                    g[i * W + q] *= l[q];
+                    s[i * W + q] = z[i * W + q];
+                }
+            }
+            rev_chain(true, s, g, 0);
+        } else {  // B_MAHAL
+            fwd_chain(true, s, 0);
+            const T w = valid ? static_cast<const T *>(a.G)[j] : (T)0;
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                const VT l = lam_chunk(i);
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const T z = s[i * W + q];
+                    lacc[i * W + q] = fmat(w * z, z, lacc[i * W + q]);
+                    g[i * W + q] = (T)2 * w * l[q] * z;
+                }
+            }
+            rev_chain(true, s, g, 0);
+        }
+        if (write_dx && valid) {
+            if (a.dX) store_vec(g, (T)1, static_cast<T *>(a.dX), a.lddx, j);
+            if constexpr (OP == B_MAHAL)
+                if (a.dXb) store_vec(g, (T)-1, static_cast<T *>(a.dXb), a.lddx, j);
+        }
+    }
+
+    // Block partials: the waves add into one LDS buffer in a fixed order.
+    T *part = static_cast<T *>(a.scratch);
+    auto emit = [&](const T(&v)[E], T *dst) {
+        for (int w = 0; w < kWPB; ++w) {
+            __syncthreads();
+            if (wave == w) {
+#pragma unroll
+                for (int i = 0; i < NC; ++i) {
+                    VT *c = reinterpret_cast<VT *>(sComb + i * STR + lane * W);
+                    VT t = (w == 0) ? VT{} : *c;
+#pragma unroll
+                    for (int q = 0; q < W; ++q) t[q] += v[i * W + q];
+                    *c = t;
+                }
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < npad; e += kThreads) dst[e] = sComb[e];
+    };
+#pragma unroll
+    for (int b = 0; b < HB; ++b)
+        if (b < kcnt) emit(acc[b], part + ((size_t)blockIdx.x * h + k0 + b) * npad);
+    if (do_lam) emit(lacc, part + (size_t)nblocks * h * npad + (size_t)blockIdx.x * npad);
+}
+
+// Fixed-order sum of the block partials, then -tau_k and the chain rule of
+// the normalisation.  Block k < h: reflector k; block h: the spectrum.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_finish(const T *__restrict__ part, int nblocks,
+                                                   int n, int h, int npad,
+                                                   const T *__restrict__ tau,
+                                                   const double *__restrict__ uh64,
+                                                   const double *__restrict__ nrm64,
+                                                   T *__restrict__ dU, int64_t lddu,
+                                                   T *__restrict__ dlam) {
+    __shared__ double red[256];
+    const int k = blockIdx.x;
+    const int t = threadIdx.x;
+    if (k == h) {
+        if (!dlam) return;
+        const T *lp = part + (size_t)nblocks * h * npad;
+        for (int e = t; e < n; e += 256) {
+            double s = 0.0;
+            for (int b = 0; b < nblocks; ++b) s += (double)lp[(size_t)b * npad + e];
+            dlam[e] = (T)s;
+        }
+        return;
+    }
+    if (!dU) return;
+    const double nrm = nrm64[k];
+    const double mt = -(double)tau[k];
+    auto g_at = [&](int e) {
+        double s = 0.0;
+        for (int b = 0; b < nblocks; ++b) s += (double)part[((size_t)b * h + k) * npad + e];
+        return mt * s;
+    };
+    double p = 0.0;
+    for (int e = t; e < n; e += 256) p += uh64[(size_t)k * n + e] * g_at(e);
+    red[t] = p;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    p = red[0];
+    for (int e = t; e < n; e += 256) {
+        double v = 0.0;
+        if (nrm > 0.0) v = (g_at(e) - p * uh64[(size_t)k * n + e]) / nrm;
+        dU[e + (int64_t)k * lddu] = (T)v;
+    }
+}
+
+size_t lds_small(hh_op op, const FusedPlan &p) {
+    const size_t es = (p.t == HH_F64) ? 8 : 4;
+    const size_t R = (op == HH_OP_SYM_BWD) ? 2 * (size_t)p.h : (size_t)p.h;
+    return 2 * (size_t)p.s.npad * es + kWPB * std::max<size_t>(R, 1) * es;
+}
+bool refl_in_lds(hh_op op, const FusedPlan &p) {
+    const size_t es = (p.t == HH_F64) ? 8 : 4;
+    return lds_small(op, p) + (size_t)p.h * p.s.npad * es <= kLdsBudget;
+}
+size_t lds_bytes_for(hh_op op, const FusedPlan &p) {
+    const size_t es = (p.t == HH_F64) ? 8 : 4;
+    return lds_small(op, p) + (refl_in_lds(op, p) ? (size_t)p.h * p.s.npad * es : 0);
+}
+
+int bwd_blocks(const FusedPlan &p) {
+    const int64_t need = (p.N + kWPB - 1) / kWPB;
+    const int64_t cap = (int64_t)device_cu_count() * 2;
+    return (int)std::max<int64_t>(1, std::min(need, cap));
+}
+
+template <typename T, int NC, bool UL>
+hipError_t launch_main(hh_op op, const FusedPlan &p, const FusedBwdArgs &a, dim3 grid,
+                       size_t lds, int k0, int kcnt, int wdx, int dl, int nb, hipStream_t st) {
+    switch (op) {
+    case HH_OP_APPLY_BWD:
+        hipLaunchKernelGGL((k_fused_bwd<T, NC, B_APPLY, UL>), grid, dim3(kThreads), lds, st, a, k0,
+                           kcnt, wdx, dl, nb);
+        break;
+    case HH_OP_APPLY_T_BWD:
+        hipLaunchKernelGGL((k_fused_bwd<T, NC, B_APPLY_T, UL>), grid, dim3(kThreads), lds, st, a, k0,
+                           kcnt, wdx, dl, nb);
+        break;
+    case HH_OP_SYM_BWD:
+        hipLaunchKernelGGL((k_fused_bwd<T, NC, B_SYM, UL>), grid, dim3(kThreads), lds, st, a, k0,
+                           kcnt, wdx, dl, nb);
+        break;
+    default:
+        hipLaunchKernelGGL((k_fused_bwd<T, NC, B_MAHAL, UL>), grid, dim3(kThreads), lds, st, a, k0,
+                           kcnt, wdx, dl, nb);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int NC>
+hipError_t run_bwd(hh_op op, const FusedPlan &p, const FusedBwdArgs &a, hipStream_t st) {
+    constexpr int HB = hb_for<T, NC>();
+    const int nb = bwd_blocks(p);
+    const size_t lds = lds_bytes_for(op, p);
+    const dim3 grid(nb);
+    const int h = (int)p.h;
+    const bool ul = refl_in_lds(op, p);
+    auto go = [&](int k0, int cnt, int wdx, int dl) {
+        return ul ? launch_main<T, NC, true>(op, p, a, grid, lds, k0, cnt, wdx, dl, nb, st)
+                  : launch_main<T, NC, false>(op, p, a, grid, lds, k0, cnt, wdx, dl, nb, st);
+    };
+    if (!a.dU || h == 0) {
+        hipError_t e = go(0, 0, 1, 1);
+        if (e != hipSuccess) return e;
+    } else {
+        for (int k0 = 0; k0 < h; k0 += HB) {
+            const int cnt = std::min(HB, h - k0);
+            hipError_t e = go(k0, cnt, k0 + HB >= h, k0 == 0);
+            if (e != hipSuccess) return e;
+        }
+    }
+    const bool has_lam = (op == HH_OP_SYM_BWD || op == HH_OP_MAHAL_BWD) && a.dlam;
+    if ((a.dU && h > 0) || has_lam) {
+        hipLaunchKernelGGL((k_bwd_finish<T>), dim3(h + 1), dim3(256), 0, st,
+                           static_cast<const T *>(a.scratch), nb, a.n, h, a.npad,
+                           static_cast<const T *>(a.tau), a.uh64, a.nrm64,
+                           static_cast<T *>(a.dU), a.lddu,
+                           has_lam ? static_cast<T *>(a.dlam) : nullptr);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t dispatch_nc(hh_op op, const FusedPlan &p, const FusedBwdArgs &a, hipStream_t st) {
+    switch (p.s.nc) {
+    case 1: return run_bwd<T, 1>(op, p, a, st);
+    case 2: return run_bwd<T, 2>(op, p, a, st);
+    case 4: return run_bwd<T, 4>(op, p, a, st);
+    case 8: return run_bwd<T, 8>(op, p, a, st);
+    case 16: return run_bwd<T, 16>(op, p, a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool fused_bwd_plan(hh_dtype t, int64_t n, int64_t h, int64_t N, FusedPlan *p) {
+    const int W = (t == HH_F64) ? 2 : 4;
+    int nc = 1;
+    while ((int64_t)nc * 64 * W < n) nc <<= 1;
+    if (nc > 16) return false;
+    p->t = t;
+    p->n = n;
+    p->h = h;
+    p->N = N;
+    p->s.lpv = 64;
+    p->s.nc = nc;
+    p->s.npad = nc * 64 * W;
+    p->hc = (int)h;
+    p->lds_bytes = 0;
+    return true;
+}
+
+bool fused_bwd_supported(hh_op op, const FusedPlan &p) {
+    return p.s.lpv == 64 && p.s.nc <= 16 && lds_bytes_for(op, p) <= kLdsBudget;
+}
+
+size_t fused_bwd_ws_bytes(hh_op op, const FusedPlan &p) {
+    (void)op;
+    const size_t es = (p.t == HH_F64) ? 8 : 4;
+    const size_t nb = (size_t)bwd_blocks(p);
+    return align256(nb * ((size_t)p.h + 1) * p.s.npad * es);
+}
+
+hipError_t launch_fused_bwd(const FusedPlan &p, hh_op op, const FusedBwdArgs &a,
+                            hipStream_t st) {
+    if (p.t == HH_F32) return dispatch_nc<float>(op, p, a, st);
+    return dispatch_nc<double>(op, p, a, st);
+}
+
+}  // namespace hh

@@ -1,0 +1,141 @@
+// Internal declarations shared by the HIP translation units of libhh.so.
+// Not part of the public ABI (that is include/hh.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "hh.h"
+
+namespace hh {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// 16-byte vector types: the unit of every global and LDS access of the fused
+// kernels (one dwordx4 per lane).
+template <typename T> struct V16;
+template <> struct V16<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static constexpr int W = 4;
+};
+template <> struct V16<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+    static constexpr int W = 2;
+};
+
+// Fused multiply-add in the operand type (never promotes float to double).
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// ---------------------------------------------------------------------------
+// Cross-lane sums built from DPP moves (no LDS round trip).
+//   quad_perm [1,0,3,2] = 0xB1, quad_perm [2,3,0,1] = 0x4E,
+//   row_ror:4 = 0x124, row_ror:8 = 0x128  -> every lane of a 16-lane row
+//   holds the row sum;  row_bcast:15 = 0x142 (rows 1,3), row_bcast:31 = 0x143
+//   (rows 2,3) -> lane 63 holds the wave sum.
+template <int CTRL, int RM = 0xF, int BM = 0xF>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, RM, BM, false));
+}
+template <int CTRL, int RM = 0xF, int BM = 0xF>
+__device__ __forceinline__ double dpp_mov(double v) {
+    unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, RM, BM, false);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, RM, BM, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned long long)(unsigned)lo);
+}
+
+template <typename T> __device__ __forceinline__ T row_sum16(T v) {
+    v += dpp_mov<0xB1>(v);
+    v += dpp_mov<0x4E>(v);
+    v += dpp_mov<0x124>(v);
+    v += dpp_mov<0x128>(v);
+    return v;
+}
+
+__device__ __forceinline__ float read_lane(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+    unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
+    unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum over the LPV lanes that share one vector; every one of them gets it.
+template <int LPV, typename T> __device__ __forceinline__ T group_sum(T v) {
+    static_assert(LPV == 16 || LPV == 64, "16 or 64 lanes per vector");
+    v = row_sum16(v);
+    if constexpr (LPV == 64) {
+        v += dpp_mov<0x142, 0xA>(v);
+        v += dpp_mov<0x143, 0xC>(v);
+        v = read_lane(v, 63);
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel selection for the fused (sequential-reflector) kernels: LPV lanes
+// own one vector, each lane NC 16-byte chunks of it; npad = NC*LPV*W >= n.
+struct FusedShape {
+    int lpv;
+    int nc;
+    int npad;
+};
+bool fused_shape(hh_dtype t, int64_t n, FusedShape *s);
+
+// Records a thread-local message for hh_last_error() and returns s.
+hh_status set_error(hh_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+// Device facts, cached per device.
+int device_cu_count();
+
+// Workspace layout helpers.
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------
+// Launchers (host side, enqueue only).  Each returns hipSuccess or the launch
+// error.  Pointers are device pointers; shapes have been validated.
+struct FusedPlan {
+    hh_dtype t;          // F32 or F64 (compute = io = param)
+    int64_t n, h, N;
+    FusedShape s;
+    int hc;              // reflectors per LDS chunk
+    size_t lds_bytes;
+};
+
+// Setup: uh (FP64), compute-type padded reflectors, tau, padded lam.
+hipError_t launch_setup_fused(hh_dtype t, const void *U, int64_t ldu, const void *lam,
+                              int64_t n, int64_t h, int npad, void *ut, void *tau,
+                              void *lamp, double *uh64, double *nrm64, hipStream_t st);
+
+enum FusedOp { F_APPLY = 0, F_APPLY_T = 1, F_SYM = 2, F_MAHAL = 3 };
+
+struct FusedFwdArgs {
+    const void *X;
+    int64_t ldx;
+    const void *Xb;
+    int64_t ldb;
+    void *Y;  // output vectors, or distances for MAHAL
+    int64_t ldy;
+    const void *ut;
+    const void *tau;
+    const void *lam;
+    int n, h, npad, hc;
+    int64_t N;
+    int vec_ok;  // 16-byte accesses are legal for every data operand
+};
+
+hipError_t launch_fused_fwd(const FusedPlan &p, FusedOp op, const FusedFwdArgs &a,
+                            hipStream_t st);
+bool fused_plan(hh_dtype t, int64_t n, int64_t h, int64_t N, FusedPlan *p);
+
+}  // namespace hh

@@ -1,0 +1,252 @@
+"""Python entry points: one torch.autograd.Function per operation of libhh.so.
+
+Tensors use the torch view of the library's column-major layout:
+  U   : (h, n)  row k is the reflector vector u_k (normalised in the library)
+  X   : (N, n)  row j is vector j
+  lam : (n,)
+Each call passes device pointers and torch's current stream to the C ABI and
+returns; no arithmetic on the data happens in Python.
+
+``compute`` selects the arithmetic: float64/float32 run the fused
+sequential-reflector kernels (data in that dtype); bfloat16/float16 run the
+compact-WY matrix-core kernels (data in that dtype or float32, parameters in
+float32).  ``algo`` may force "fused" or "wy"; the default "auto" follows
+``compute``.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+_FUSED = (torch.float64, torch.float32)
+
+
+def _cfg(X: torch.Tensor, compute):
+    io = X.dtype
+    comp = io if compute is None else compute
+    param = comp if comp in _FUSED else torch.float32
+    return param, io, comp
+
+
+def _rows(t: torch.Tensor) -> torch.Tensor:
+    if t.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        t = t.contiguous()
+    return t
+
+
+def _param(t, dtype):
+    if t is None:
+        return None
+    t = t.to(dtype)
+    return t.contiguous()
+
+
+def _check_dev(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("libhh operates on device tensors")
+
+
+# --------------------------------------------------------------------------
+# raw calls (no autograd)
+# --------------------------------------------------------------------------
+def apply_raw(U, X, trans=False, compute=None, algo="auto", out=None):
+    _check_dev(U, X)
+    X = _rows(X)
+    param, io, comp = _cfg(X, compute)
+    U = _param(U, param)
+    N, n = X.shape
+    h = U.shape[0]
+    desc = L.make_desc(n, h, N, param, io, comp, algo)
+    Y = torch.empty((N, n), dtype=io, device=X.device) if out is None else out
+    op = L.HH_OP_APPLY_T if trans else L.HH_OP_APPLY
+    ws = L.workspace(op, desc, X.device)
+    fn = L.lib().hh_apply_T if trans else L.lib().hh_apply
+    L.check("hh_apply_T" if trans else "hh_apply",
+            fn(ctypes.byref(desc), L.ptr(U), max(n, U.stride(0) if h else n), L.ptr(X), L.ld(X),
+               L.ptr(Y), L.ld(Y), L.ptr(ws), ws.numel(), L.stream_of(X)))
+    return Y
+
+
+def sym_raw(U, lam, X, compute=None, algo="auto", out=None):
+    _check_dev(U, lam, X)
+    X = _rows(X)
+    param, io, comp = _cfg(X, compute)
+    U, lam = _param(U, param), _param(lam, param)
+    N, n = X.shape
+    h = U.shape[0]
+    desc = L.make_desc(n, h, N, param, io, comp, algo)
+    Y = torch.empty((N, n), dtype=io, device=X.device) if out is None else out
+    ws = L.workspace(L.HH_OP_SYM, desc, X.device)
+    L.check("hh_sym_apply", L.lib().hh_sym_apply(
+        ctypes.byref(desc), L.ptr(U), max(n, U.stride(0) if h else n), L.ptr(lam), L.ptr(X),
+        L.ld(X), L.ptr(Y), L.ld(Y), L.ptr(ws), ws.numel(), L.stream_of(X)))
+    return Y
+
+
+def mahal_raw(U, lam, Xa, Xb, compute=None, algo="auto"):
+    _check_dev(U, lam, Xa, Xb)
+    Xa, Xb = _rows(Xa), _rows(Xb)
+    param, io, comp = _cfg(Xa, compute)
+    U, lam = _param(U, param), _param(lam, param)
+    N, n = Xa.shape
+    h = U.shape[0]
+    desc = L.make_desc(n, h, N, param, io, comp, algo)
+    d = torch.empty((N,), dtype=param, device=Xa.device)
+    ws = L.workspace(L.HH_OP_MAHAL, desc, Xa.device)
+    L.check("hh_mahalanobis", L.lib().hh_mahalanobis(
+        ctypes.byref(desc), L.ptr(U), max(n, U.stride(0) if h else n), L.ptr(lam), L.ptr(Xa),
+        L.ld(Xa), L.ptr(Xb), L.ld(Xb), L.ptr(d), L.ptr(ws), ws.numel(), L.stream_of(Xa)))
+    return d
+
+
+def apply_bwd_raw(U, X, dY, trans=False, compute=None, algo="auto", need_dX=True, need_dU=True):
+    _check_dev(U, X, dY)
+    X, dY = _rows(X), _rows(dY.to(X.dtype))
+    param, io, comp = _cfg(X, compute)
+    U = _param(U, param)
+    N, n = X.shape
+    h = U.shape[0]
+    desc = L.make_desc(n, h, N, param, io, comp, algo)
+    dX = torch.empty((N, n), dtype=io, device=X.device) if need_dX else None
+    dU = torch.empty((h, n), dtype=param, device=X.device) if need_dU else None
+    op = L.HH_OP_APPLY_T_BWD if trans else L.HH_OP_APPLY_BWD
+    ws = L.workspace(op, desc, X.device)
+    fn = L.lib().hh_apply_T_backward if trans else L.lib().hh_apply_backward
+    L.check("hh_apply_T_backward" if trans else "hh_apply_backward",
+            fn(ctypes.byref(desc), L.ptr(U), max(n, U.stride(0) if h else n), L.ptr(X), L.ld(X),
+               L.ptr(dY), L.ld(dY), L.ptr(dX), n if dX is None else L.ld(dX), L.ptr(dU), n,
+               L.ptr(ws), ws.numel(), L.stream_of(X)))
+    return dX, dU
+
+
+def sym_bwd_raw(U, lam, X, dY, compute=None, algo="auto", need_dX=True, need_dU=True,
+                need_dlam=True):
+    _check_dev(U, lam, X, dY)
+    X, dY = _rows(X), _rows(dY.to(X.dtype))
+    param, io, comp = _cfg(X, compute)
+    U, lam = _param(U, param), _param(lam, param)
+    N, n = X.shape
+    h = U.shape[0]
+    desc = L.make_desc(n, h, N, param, io, comp, algo)
+    dX = torch.empty((N, n), dtype=io, device=X.device) if need_dX else None
+    dU = torch.empty((h, n), dtype=param, device=X.device) if need_dU else None
+    dlam = torch.empty((n,), dtype=param, device=X.device) if need_dlam else None
+    ws = L.workspace(L.HH_OP_SYM_BWD, desc, X.device)
+    L.check("hh_sym_apply_backward", L.lib().hh_sym_apply_backward(
+        ctypes.byref(desc), L.ptr(U), max(n, U.stride(0) if h else n), L.ptr(lam), L.ptr(X),
+        L.ld(X), L.ptr(dY), L.ld(dY), L.ptr(dX), n if dX is None else L.ld(dX), L.ptr(dU), n,
+        L.ptr(dlam), L.ptr(ws), ws.numel(), L.stream_of(X)))
+    return dX, dU, dlam
+
+
+def mahal_bwd_raw(U, lam, Xa, Xb, dd, compute=None, algo="auto", need_dX=True, need_dU=True,
+                  need_dlam=True):
+    _check_dev(U, lam, Xa, Xb, dd)
+    Xa, Xb = _rows(Xa), _rows(Xb)
+    param, io, comp = _cfg(Xa, compute)
+    U, lam, dd = _param(U, param), _param(lam, param), _param(dd, param)
+    N, n = Xa.shape
+    h = U.shape[0]
+    desc = L.make_desc(n, h, N, param, io, comp, algo)
+    dXa = torch.empty((N, n), dtype=io, device=Xa.device) if need_dX else None
+    dXb = torch.empty((N, n), dtype=io, device=Xa.device) if need_dX else None
+    dU = torch.empty((h, n), dtype=param, device=Xa.device) if need_dU else None
+    dlam = torch.empty((n,), dtype=param, device=Xa.device) if need_dlam else None
+    ws = L.workspace(L.HH_OP_MAHAL_BWD, desc, Xa.device)
+    L.check("hh_mahalanobis_backward", L.lib().hh_mahalanobis_backward(
+        ctypes.byref(desc), L.ptr(U), max(n, U.stride(0) if h else n), L.ptr(lam), L.ptr(Xa),
+        L.ld(Xa), L.ptr(Xb), L.ld(Xb), L.ptr(dd), L.ptr(dXa), L.ptr(dXb), n, L.ptr(dU), n,
+        L.ptr(dlam), L.ptr(ws), ws.numel(), L.stream_of(Xa)))
+    return dXa, dXb, dU, dlam
+
+
+# --------------------------------------------------------------------------
+# autograd
+# --------------------------------------------------------------------------
+class _Apply(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U, X, trans, compute, algo):
+        ctx.cfg = (trans, compute, algo)
+        ctx.save_for_backward(U, X)
+        return apply_raw(U, X, trans, compute, algo)
+
+    @staticmethod
+    def backward(ctx, dY):
+        U, X = ctx.saved_tensors
+        trans, compute, algo = ctx.cfg
+        dX, dU = apply_bwd_raw(U, X, dY, trans, compute, algo,
+                               need_dX=ctx.needs_input_grad[1], need_dU=ctx.needs_input_grad[0])
+        if dU is not None:
+            dU = dU.to(U.dtype)
+        return dU, dX, None, None, None
+
+
+class _Sym(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U, lam, X, compute, algo):
+        ctx.cfg = (compute, algo)
+        ctx.save_for_backward(U, lam, X)
+        return sym_raw(U, lam, X, compute, algo)
+
+    @staticmethod
+    def backward(ctx, dY):
+        U, lam, X = ctx.saved_tensors
+        compute, algo = ctx.cfg
+        dX, dU, dlam = sym_bwd_raw(U, lam, X, dY, compute, algo,
+                                   need_dX=ctx.needs_input_grad[2],
+                                   need_dU=ctx.needs_input_grad[0],
+                                   need_dlam=ctx.needs_input_grad[1])
+        if dU is not None:
+            dU = dU.to(U.dtype)
+        if dlam is not None:
+            dlam = dlam.to(lam.dtype)
+        return dU, dlam, dX, None, None
+
+
+class _Mahal(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U, lam, Xa, Xb, compute, algo):
+        ctx.cfg = (compute, algo)
+        ctx.save_for_backward(U, lam, Xa, Xb)
+        return mahal_raw(U, lam, Xa, Xb, compute, algo)
+
+    @staticmethod
+    def backward(ctx, dd):
+        U, lam, Xa, Xb = ctx.saved_tensors
+        compute, algo = ctx.cfg
+        need_x = ctx.needs_input_grad[2] or ctx.needs_input_grad[3]
+        dXa, dXb, dU, dlam = mahal_bwd_raw(U, lam, Xa, Xb, dd.contiguous(), compute, algo,
+                                           need_dX=need_x, need_dU=ctx.needs_input_grad[0],
+                                           need_dlam=ctx.needs_input_grad[1])
+        if dU is not None:
+            dU = dU.to(U.dtype)
+        if dlam is not None:
+            dlam = dlam.to(lam.dtype)
+        return (dU, dlam, dXa if ctx.needs_input_grad[2] else None,
+                dXb if ctx.needs_input_grad[3] else None, None, None)
+
+
+def apply(U, X, *, compute=None, algo="auto"):
+    """Y = Q X with Q = H_1 ... H_h (rows of the result are Q x_j)."""
+    return _Apply.apply(U, X, False, compute, algo)
+
+
+def apply_T(U, X, *, compute=None, algo="auto"):
+    """Y = Q^T X = H_h ... H_1 X."""
+    return _Apply.apply(U, X, True, compute, algo)
+
+
+def sym_apply(U, lam, X, *, compute=None, algo="auto"):
+    """Y = Q diag(lam) Q^T X."""
+    return _Sym.apply(U, lam, X, compute, algo)
+
+
+def mahalanobis(U, lam, Xa, Xb, *, compute=None, algo="auto"):
+    """d_j = sum_i lam_i ((Q^T (xa_j - xb_j))_i)^2."""
+    return _Mahal.apply(U, lam, Xa, Xb, compute, algo)

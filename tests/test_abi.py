@@ -1,0 +1,109 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol that
+include/hh.h declares, and validates arguments before touching a device.
+No compute call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1811_07624_amd as P
+from paper_1811_07624_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"HH_API[^;(]*?\b(hh_\w+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ("hh_apply", "hh_apply_T", "hh_sym_apply", "hh_mahalanobis", "hh_apply_backward",
+              "hh_apply_T_backward", "hh_sym_apply_backward", "hh_mahalanobis_backward",
+              "hh_workspace_size"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.lib()
+    for s in declared_symbols():
+        assert hasattr(lib, s), s
+    assert set(L.EXPORTS) <= set(declared_symbols())
+
+
+def _desc(n=8, h=2, N=4, p=L.HH_F32, io=L.HH_F32, c=L.HH_F32, algo=L.HH_ALGO_AUTO):
+    return L.HHDesc(n, h, N, p, io, c, algo)
+
+
+def _apply(desc, U=1, ldu=8, X=2, ldx=8, Y=3, ldy=8, ws=None, wsb=0):
+    # fake non-null pointers: every failure below is caught before any launch
+    v = ctypes.c_void_p
+    return P.lib().hh_apply(ctypes.byref(desc), v(U), ldu, v(X), ldx, v(Y), ldy, v(ws) if ws else None,
+                            wsb, None)
+
+
+@pytest.mark.parametrize("field,value", [("n", 0), ("h", -1), ("N", -5)])
+def test_invalid_shapes(field, value):
+    d = _desc()
+    setattr(d, field, value)
+    assert _apply(d) == L.HH_ERR_INVALID_ARG
+    assert P.lib().hh_last_error().decode() != ""
+
+
+def test_invalid_leading_dimension():
+    assert _apply(_desc(), ldx=7) == L.HH_ERR_INVALID_ARG
+    assert b"ldx" in P.lib().hh_last_error()
+    assert _apply(_desc(), ldy=3) == L.HH_ERR_INVALID_ARG
+
+
+def test_unsupported_combinations():
+    # FUSED with mixed dtypes
+    assert _apply(_desc(p=L.HH_F64)) == L.HH_ERR_UNSUPPORTED
+    # WY with F64 parameters
+    assert _apply(_desc(p=L.HH_F64, io=L.HH_BF16, c=L.HH_BF16)) == L.HH_ERR_UNSUPPORTED
+    # FUSED forced on a 16-bit compute type
+    assert _apply(_desc(c=L.HH_BF16, algo=L.HH_ALGO_FUSED)) == L.HH_ERR_UNSUPPORTED
+    # fused kernels cover n <= 8192 (FP32)
+    assert _apply(_desc(n=8193), ldu=8193, ldx=8193, ldy=8193) == L.HH_ERR_UNSUPPORTED
+
+
+def test_null_pointers_and_workspace():
+    d = _desc()
+    nb = ctypes.c_size_t(0)
+    assert P.lib().hh_workspace_size(L.HH_OP_APPLY, ctypes.byref(d), ctypes.byref(nb)) == L.HH_OK
+    assert nb.value > 0
+    assert _apply(d, X=0, ws=16, wsb=nb.value) == L.HH_ERR_INVALID_ARG
+    assert _apply(d, ws=16, wsb=nb.value - 1) == L.HH_ERR_WORKSPACE
+    assert _apply(d, ws=None, wsb=0) in (L.HH_ERR_INVALID_ARG, L.HH_ERR_WORKSPACE)
+
+
+def test_in_place_needs_equal_ld():
+    d = _desc()
+    nb = ctypes.c_size_t(0)
+    P.lib().hh_workspace_size(L.HH_OP_APPLY, ctypes.byref(d), ctypes.byref(nb))
+    assert _apply(d, X=64, Y=64, ldx=8, ldy=16, ws=16, wsb=nb.value) == L.HH_ERR_INVALID_ARG
+
+
+def test_n_zero_batch_is_noop():
+    d = _desc(N=0)
+    # N = 0: nothing is enqueued, so fake pointers are never touched
+    assert _apply(d, X=0, Y=0, ws=None, wsb=0) == L.HH_OK
+
+
+def test_workspace_size_all_ops():
+    for op in range(8):
+        for (p, io, c) in [(L.HH_F32, L.HH_F32, L.HH_F32), (L.HH_F64, L.HH_F64, L.HH_F64)]:
+            d = _desc(n=512, h=9, N=1000, p=p, io=io, c=c)
+            nb = ctypes.c_size_t(0)
+            assert P.lib().hh_workspace_size(op, ctypes.byref(d), ctypes.byref(nb)) == L.HH_OK
+
+
+def test_status_strings():
+    for s in range(5):
+        assert P.lib().hh_status_string(s)
