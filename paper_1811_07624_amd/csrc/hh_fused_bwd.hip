@@ -21,11 +21,22 @@
 // (deterministic for a given grid), scales by -tau_k and applies the chain
 // rule of the normalisation uh = u/||u||: dU = (I - uh uh^T) dL/duh / ||u||.
 #include <algorithm>
+#include <type_traits>
+#include <utility>
 
 #include "hh_bwd.h"
 
 namespace hh {
 namespace {
+
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+// Calls f(integral_constant<int, i>) for i = 0 .. N-1 (compile-time indices).
+template <int N, typename F> __device__ __forceinline__ void static_for(F &&f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 constexpr int kWPB = 4;
 constexpr int kThreads = kWPB * kWave;
@@ -123,28 +134,46 @@ __global__ __launch_bounds__(kThreads) void k_fused_bwd(FusedBwdArgs a, int k0, 
             axpy(-p * gTau[k], uv, s);
         }
     };
-    // reverse sweep: rebuilds s_{r-1}, propagates g, accumulates dL/du.
+    // One reverse step for reflector k at chain position r: rebuilds s_{r-1},
+    // propagates g and, when ACC, accumulates dL/du into acc[B].
+    auto rev_step = [&](auto accb, int k, int r, T(&s)[E], T(&g)[E], int abase) {
+        constexpr int B = decltype(accb)::value;
+        VT uv[NC];
+        load_u(k, uv);
+        const T beta = dot(uv, g);
+        const T p = myAl[abase + r];
+        const T t = gTau[k];
+        axpy(t * p, uv, s);  // s <- s_{r-1}
+        if constexpr (B >= 0) {
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                acc[B][e] = fmat(p, g[e], fmat(beta, s[e], acc[B][e]));
+        }
+        axpy(-t * beta, uv, g);
+    };
+    using NoAcc = std::integral_constant<int, -1>;
+    // reverse sweep over one chain.  The accumulated window k0 .. k0+kcnt-1 is
+    // a contiguous run of steps, walked with compile-time accumulator slots.
     auto rev_chain = [&](bool up, T(&s)[E], T(&g)[E], int abase) {
+        const int kw = k0 + kcnt;
+        if (up) {  // reverse visits k = h-1 .. 0, position r = k
 #pragma unroll 1
-        for (int r = h - 1; r >= 0; --r) {
-            const int k = up ? r : h - 1 - r;
-            VT uv[NC];
-            load_u(k, uv);
-            const T beta = dot(uv, g);
-            const T p = myAl[abase + r];
-            const T t = gTau[k];
-            axpy(t * p, uv, s);  // s <- s_{r-1}
-            const int kb = k - k0;
-            if (kb >= 0 && kb < kcnt) {
-#pragma unroll
-                for (int b = 0; b < HB; ++b)
-                    if (b == kb) {
-#pragma unroll
-                        for (int e = 0; e < E; ++e)
-                            acc[b][e] = fmat(p, g[e], fmat(beta, s[e], acc[b][e]));
-                    }
-            }
-            axpy(-t * beta, uv, g);
+            for (int k = h - 1; k >= kw; --k) rev_step(NoAcc{}, k, k, s, g, abase);
+            static_for<HB>([&](auto bb) {
+                constexpr int b = HB - 1 - decltype(bb)::value;
+                if (b < kcnt) rev_step(std::integral_constant<int, b>{}, k0 + b, k0 + b, s, g, abase);
+            });
+#pragma unroll 1
+            for (int k = k0 - 1; k >= 0; --k) rev_step(NoAcc{}, k, k, s, g, abase);
+        } else {   // reverse visits k = 0 .. h-1, position r = h-1-k
+#pragma unroll 1
+            for (int k = 0; k < k0; ++k) rev_step(NoAcc{}, k, h - 1 - k, s, g, abase);
+            static_for<HB>([&](auto bb) {
+                constexpr int b = decltype(bb)::value;
+                if (b < kcnt) rev_step(std::integral_constant<int, b>{}, k0 + b, h - 1 - k0 - b, s, g, abase);
+            });
+#pragma unroll 1
+            for (int k = kw; k < h; ++k) rev_step(NoAcc{}, k, h - 1 - k, s, g, abase);
         }
     };
     auto load_vec = [&](T(&x)[E], const T *base, int64_t ld, int64_t j, bool valid) {
@@ -273,55 +302,61 @@ __global__ __launch_bounds__(kThreads) void k_fused_bwd(FusedBwdArgs a, int k0, 
         __syncthreads();
         for (int e = tid; e < npad; e += kThreads) dst[e] = sComb[e];
     };
-#pragma unroll
-    for (int b = 0; b < HB; ++b)
+    static_for<HB>([&](auto bb) {
+        constexpr int b = decltype(bb)::value;
         if (b < kcnt) emit(acc[b], part + ((size_t)blockIdx.x * h + k0 + b) * npad);
+    });
     if (do_lam) emit(lacc, part + (size_t)nblocks * h * npad + (size_t)blockIdx.x * npad);
 }
 
-// Fixed-order sum of the block partials, then -tau_k and the chain rule of
-// the normalisation.  Block k < h: reflector k; block h: the spectrum.
+// Fixed-order FP64 sum of the block partials: grid (npad/256, h+1); row h is
+// the spectrum gradient, written straight to dlam.
 template <typename T>
-__global__ __launch_bounds__(256) void k_bwd_finish(const T *__restrict__ part, int nblocks,
-                                                   int n, int h, int npad,
-                                                   const T *__restrict__ tau,
+__global__ __launch_bounds__(256) void k_bwd_reduce(const T *__restrict__ part, int nblocks,
+                                                   int n, int h, int npad, int kfirst,
+                                                   double *__restrict__ red,
+                                                   T *__restrict__ dlam) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int k = kfirst + (int)blockIdx.y;
+    if (e >= n) return;
+    double s = 0.0;
+    if (k < h) {
+        for (int b = 0; b < nblocks; ++b) s += (double)part[((size_t)b * h + k) * npad + e];
+        red[(size_t)k * npad + e] = s;
+    } else if (dlam) {
+        const T *lp = part + (size_t)nblocks * h * npad;
+        for (int b = 0; b < nblocks; ++b) s += (double)lp[(size_t)b * npad + e];
+        dlam[e] = (T)s;
+    }
+}
+
+// -tau_k and the chain rule of the normalisation, one block per reflector:
+// dU_k = (I - uh_k uh_k^T) g_k / ||u_k||, g_k = -tau_k * (summed partials).
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_finish(const double *__restrict__ red, int n,
+                                                   int npad, const T *__restrict__ tau,
                                                    const double *__restrict__ uh64,
                                                    const double *__restrict__ nrm64,
-                                                   T *__restrict__ dU, int64_t lddu,
-                                                   T *__restrict__ dlam) {
-    __shared__ double red[256];
+                                                   T *__restrict__ dU, int64_t lddu) {
+    __shared__ double sred[256];
     const int k = blockIdx.x;
     const int t = threadIdx.x;
-    if (k == h) {
-        if (!dlam) return;
-        const T *lp = part + (size_t)nblocks * h * npad;
-        for (int e = t; e < n; e += 256) {
-            double s = 0.0;
-            for (int b = 0; b < nblocks; ++b) s += (double)lp[(size_t)b * npad + e];
-            dlam[e] = (T)s;
-        }
-        return;
-    }
-    if (!dU) return;
     const double nrm = nrm64[k];
     const double mt = -(double)tau[k];
-    auto g_at = [&](int e) {
-        double s = 0.0;
-        for (int b = 0; b < nblocks; ++b) s += (double)part[((size_t)b * h + k) * npad + e];
-        return mt * s;
-    };
+    const double *g = red + (size_t)k * npad;
+    const double *u = uh64 + (size_t)k * n;
     double p = 0.0;
-    for (int e = t; e < n; e += 256) p += uh64[(size_t)k * n + e] * g_at(e);
-    red[t] = p;
+    for (int e = t; e < n; e += 256) p += u[e] * (mt * g[e]);
+    sred[t] = p;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) red[t] += red[t + s];
+        if (t < s) sred[t] += sred[t + s];
         __syncthreads();
     }
-    p = red[0];
+    p = sred[0];
     for (int e = t; e < n; e += 256) {
         double v = 0.0;
-        if (nrm > 0.0) v = (g_at(e) - p * uh64[(size_t)k * n + e]) / nrm;
+        if (nrm > 0.0) v = (mt * g[e] - p * u[e]) / nrm;
         dU[e + (int64_t)k * lddu] = (T)v;
     }
 }
@@ -338,6 +373,11 @@ bool refl_in_lds(hh_op op, const FusedPlan &p) {
 size_t lds_bytes_for(hh_op op, const FusedPlan &p) {
     const size_t es = (p.t == HH_F64) ? 8 : 4;
     return lds_small(op, p) + (refl_in_lds(op, p) ? (size_t)p.h * p.s.npad * es : 0);
+}
+
+size_t partial_bytes(const FusedPlan &p, int nb) {
+    const size_t es = (p.t == HH_F64) ? 8 : 4;
+    return align256((size_t)nb * ((size_t)p.h + 1) * p.s.npad * es);
 }
 
 int bwd_blocks(const FusedPlan &p) {
@@ -393,12 +433,24 @@ hipError_t run_bwd(hh_op op, const FusedPlan &p, const FusedBwdArgs &a, hipStrea
         }
     }
     const bool has_lam = (op == HH_OP_SYM_BWD || op == HH_OP_MAHAL_BWD) && a.dlam;
-    if ((a.dU && h > 0) || has_lam) {
-        hipLaunchKernelGGL((k_bwd_finish<T>), dim3(h + 1), dim3(256), 0, st,
+    const bool has_u = a.dU && h > 0;
+    if (has_u || has_lam) {
+        double *red = reinterpret_cast<double *>(static_cast<char *>(a.scratch) +
+                                                 partial_bytes(p, nb));
+        const dim3 rgrid((a.n + 255) / 256, has_u ? h + 1 : 1);
+        // with no dU wanted the single grid row handles the spectrum (k = h)
+        hipLaunchKernelGGL((k_bwd_reduce<T>), rgrid, dim3(256), 0, st,
                            static_cast<const T *>(a.scratch), nb, a.n, h, a.npad,
+                           has_u ? 0 : h, red, has_lam ? static_cast<T *>(a.dlam) : nullptr);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (has_u) {
+        double *red = reinterpret_cast<double *>(static_cast<char *>(a.scratch) +
+                                                 partial_bytes(p, nb));
+        hipLaunchKernelGGL((k_bwd_finish<T>), dim3(h), dim3(256), 0, st, red, a.n, a.npad,
                            static_cast<const T *>(a.tau), a.uh64, a.nrm64,
-                           static_cast<T *>(a.dU), a.lddu,
-                           has_lam ? static_cast<T *>(a.dlam) : nullptr);
+                           static_cast<T *>(a.dU), a.lddu);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -441,9 +493,7 @@ bool fused_bwd_supported(hh_op op, const FusedPlan &p) {
 
 size_t fused_bwd_ws_bytes(hh_op op, const FusedPlan &p) {
     (void)op;
-    const size_t es = (p.t == HH_F64) ? 8 : 4;
-    const size_t nb = (size_t)bwd_blocks(p);
-    return align256(nb * ((size_t)p.h + 1) * p.s.npad * es);
+    return partial_bytes(p, bwd_blocks(p)) + align256(((size_t)p.h + 1) * p.s.npad * 8);
 }
 
 hipError_t launch_fused_bwd(const FusedPlan &p, hh_op op, const FusedBwdArgs &a,
