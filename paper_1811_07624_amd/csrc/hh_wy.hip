@@ -44,6 +44,9 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kWaves = 8;
+#ifndef WY_DEPTH
+#define WY_DEPTH 3  // row groups of reflector operands fetched ahead of use
+#endif
 constexpr int kThreadsWY = kWaves * kWave;
 
 // 16-bit element types used on the matrix cores.
@@ -63,6 +66,25 @@ struct F16 {
 };
 
 enum WyOp { W_APPLY = 0, W_APPLY_T = 1, W_SYM = 2 };
+
+// ---------------------------------------------------------------------------
+// Fragment-ordered copies of the reflector matrix.  Every operand load of the
+// main kernel then reads one contiguous 1 KB block (64 lanes x 16 bytes).
+//   Yc (GEMM1 A operand, lane = (c, g)): element (h, row) with
+//     h = 16 hb + c, row = 32 q + 8 g + j  at  ((hb * NQ + q) * 64 + 16 g + c) * 8 + j
+//   Yr (GEMM2 A operand): element (h, row) with row = 32 q + 8 (c/4) + 4 m + c%4,
+//     h = 32 ks + 8 g + j  at  (((q * 2 + m) * KS + ks) * 64 + 16 g + c) * 8 + j
+// with NQ = npad / 32 and KS = hp / 32.
+__device__ __forceinline__ int64_t yc_index(int h, int row, int npad) {
+    const int hb = h >> 4, c = h & 15, q = row >> 5, g = (row >> 3) & 3, j = row & 7;
+    return ((int64_t)(hb * (npad >> 5) + q) * 64 + 16 * g + c) * 8 + j;
+}
+__device__ __forceinline__ int64_t yr_index(int h, int row, int hp) {
+    const int q = row >> 5, rr = row & 31;
+    const int c = 4 * (rr >> 3) + (rr & 3), m = (rr >> 2) & 1;
+    const int ks = h >> 5, g = (h >> 3) & 3, j = h & 7;
+    return ((int64_t)((q * 2 + m) * (hp >> 5) + ks) * 64 + 16 * g + c) * 8 + j;
+}
 
 // ---------------------------------------------------------------------------
 // Setup kernels (FP64).
@@ -97,8 +119,8 @@ __global__ __launch_bounds__(256) void k_wy_norm(const float *__restrict__ U, in
         double v = 0.0;
         if (k < h && i < n && r > 0.0) v = (double)U[(int64_t)k * ldu + i] / r;
         const el y = (el)v;
-        Yc[(int64_t)k * npad + i] = y;
-        Yr[(int64_t)i * hp + k] = y;
+        Yc[yc_index(k, i, npad)] = y;
+        Yr[yr_index(k, i, hp)] = y;
         if (uh64 && k < h && i < n) uh64[(int64_t)k * n + i] = v;
         const double yd = (double)y;
         s2 += yd * yd;
@@ -121,12 +143,14 @@ __global__ __launch_bounds__(256) void k_wy_gram(const typename E::elem *__restr
                                                 int npad, int hp, double *__restrict__ G) {
     __shared__ double red[256];
     const int a = blockIdx.y, b = blockIdx.x;
-    if (b <= a) return;
     const int t = threadIdx.x;
-    const typename E::elem *ya = Yc + (int64_t)a * npad;
-    const typename E::elem *yb = Yc + (int64_t)b * npad;
+    if (b <= a) {
+        if (t == 0) G[a * hp + b] = 0.0;
+        return;
+    }
     double s = 0.0;
-    for (int i = t; i < npad; i += 256) s += (double)ya[i] * (double)yb[i];
+    for (int i = t; i < npad; i += 256)
+        s += (double)Yc[yc_index(a, i, npad)] * (double)Yc[yc_index(b, i, npad)];
     red[t] = s;
     __syncthreads();
     for (int q = 128; q > 0; q >>= 1) {
@@ -136,23 +160,52 @@ __global__ __launch_bounds__(256) void k_wy_gram(const typename E::elem *__restr
     if (t == 0) G[a * hp + b] = red[0];
 }
 
-// T = (diag(||y_k||^2/2) + striu(G))^{-1}, upper triangular, by column-wise
-// back substitution in FP64 (thread j owns column j).  Tm = T as FP32,
-// row-major; Tw = T in FP64 (kept for the backward pass).
+// T = (diag(||y_k||^2/2) + striu(G))^{-1}, upper triangular, in FP64.  Rows
+// are solved bottom-up, all columns of a row in parallel:
+//   T[i][j] = (delta_ij - sum_{k=i+1..j} G[i][k] T[k][j]) / d_i,  j >= i.
+// One LDS array holds both matrices: G transposed below the diagonal
+// (M[k][i] = G[i][k], k > i) and T on and above it.  Tm = T as FP32,
+// row-major; Tw = T in FP64 (zero below the diagonal).
 __global__ __launch_bounds__(256) void k_wy_tmat(const double *__restrict__ G,
                                                 const double *__restrict__ nrm2, int hp,
                                                 double *__restrict__ Tw, float *__restrict__ Tm) {
-    const int j = threadIdx.x;
-    if (j >= hp) return;
-    auto dg = [&](int i) { return nrm2[i] > 0.0 ? 0.5 * nrm2[i] : 0.5; };
-    for (int i = j + 1; i < hp; ++i) Tw[i * hp + j] = 0.0;
-    Tw[j * hp + j] = 1.0 / dg(j);
-    for (int i = j - 1; i >= 0; --i) {
-        double s = 0.0;
-        for (int k = i + 1; k <= j; ++k) s += G[i * hp + k] * Tw[k * hp + j];
-        Tw[i * hp + j] = -s / dg(i);
+    extern __shared__ double M[];
+    const int t = threadIdx.x;
+    // hp * hp is a multiple of 256*16 for hp in {64, 128}: unrolled, all loads in flight
+    const int per = hp * hp / 256;
+#pragma unroll 16
+    for (int r = 0; r < per; ++r) {
+        const int idx = r * 256 + t;
+        const int i = idx / hp, k = idx % hp;
+        const double v = G[idx];
+        if (i < k) M[k * hp + i] = v;
     }
-    for (int i = 0; i < hp; ++i) Tm[i * hp + j] = (float)Tw[i * hp + j];
+    __syncthreads();
+    const int j = t;
+    for (int i = hp - 1; i >= 0; --i) {
+        if (j >= i && j < hp) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int k = i + 1;
+            for (; k + 3 <= j; k += 4) {
+                a0 += M[k * hp + i] * M[k * hp + j];
+                a1 += M[(k + 1) * hp + i] * M[(k + 1) * hp + j];
+                a2 += M[(k + 2) * hp + i] * M[(k + 2) * hp + j];
+                a3 += M[(k + 3) * hp + i] * M[(k + 3) * hp + j];
+            }
+            for (; k <= j; ++k) a0 += M[k * hp + i] * M[k * hp + j];
+            const double d = nrm2[i] > 0.0 ? 0.5 * nrm2[i] : 0.5;
+            M[i * hp + j] = ((i == j ? 1.0 : 0.0) - ((a0 + a1) + (a2 + a3))) / d;
+        }
+        __syncthreads();
+    }
+#pragma unroll 16
+    for (int r = 0; r < per; ++r) {
+        const int idx = r * 256 + t;
+        const int i = idx / hp, k = idx % hp;
+        const double v = (k >= i) ? M[idx] : 0.0;
+        Tw[idx] = v;
+        Tm[idx] = (float)v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -182,13 +235,19 @@ template <typename V>
 __device__ __forceinline__ V bload(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
     return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
+// Forces v to be materialised here (an empty asm that reads and writes it),
+// so the optimiser cannot sink its computation towards a distant use.
+template <typename V> __device__ __forceinline__ void pin(V &v) { asm volatile("" : "+v"(v)); }
+
 template <typename V>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, V v, int voff, int soff) {
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, v), r, voff, soff, 0);
 }
 
-template <typename E, int P, int CB, int HP, int OP>
-__global__ __launch_bounds__(kThreadsWY) void k_wy_fwd(WyArgs a) {
+// MINB blocks per CU: HIP's second launch-bounds argument is the minimum
+// number of waves per SIMD (2 per block of 8 waves).
+template <typename E, int P, int CB, int HP, int OP, int MINB>
+__global__ __launch_bounds__(kThreadsWY, 2 * MINB) void k_wy_fwd(WyArgs a) {
     using el = typename E::elem;
     using v8 = typename E::vec8;
     constexpr int NB = 16 * CB;   // vectors per tile
@@ -196,9 +255,14 @@ __global__ __launch_bounds__(kThreadsWY) void k_wy_fwd(WyArgs a) {
     constexpr int KS = HP / 32;   // K steps of GEMM2
     constexpr int SLICE = 32 * P; // rows per wave
     extern __shared__ __align__(16) unsigned char smem[];
-    float *sP = reinterpret_cast<float *>(smem);                  // [kWaves][HP][NB]
-    float *sT = sP + kWaves * HP * NB;                            // [HP][HP]
-    el *sB = reinterpret_cast<el *>(sT + HP * HP);                // [2][CB][16][HP]
+    // LDS row strides are padded so that the lanes of one access fall in
+    // different banks.
+    constexpr int NBP = NB + 4;   // partial sums row stride
+    constexpr int HTP = HP + 1;   // T row stride
+    constexpr int HBP = HP + 8;   // W' fragment row stride (keeps 16-byte alignment)
+    float *sP = reinterpret_cast<float *>(smem);                  // [kWaves][HP][NBP]
+    float *sT = sP + kWaves * HP * NBP;                           // [HP][HTP]
+    el *sB = reinterpret_cast<el *>(sT + ((HP * HTP + 3) & ~3));  // [2][CB][16][HBP]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -212,13 +276,14 @@ __global__ __launch_bounds__(kThreadsWY) void k_wy_fwd(WyArgs a) {
     const el *X = static_cast<const el *>(a.X);
     el *Yo = static_cast<el *>(a.Y);
 
-    for (int i = tid; i < HP * HP; i += kThreadsWY) sT[i] = a.Tm[i];
+    for (int i = tid; i < HP * HP; i += kThreadsWY) sT[(i / HP) * HTP + i % HP] = a.Tm[i];
     __syncthreads();
 
-    // lane parts of the buffer offsets (bytes)
-    const int vo_yc = ((c * npad) + row0 + 8 * g) * 2;             // + hb*16*npad*2
-    const int rsub = 8 * (c >> 2) + (c & 3);                       // GEMM2 A-operand row
-    const int vo_yr = ((row0 + rsub) * HP + 8 * g) * 2;            // + (4m*HP + 32ks)*2
+    // lane parts of the buffer offsets (bytes) into the fragment-ordered
+    // reflector copies; the (hb, p, m, ks) parts are uniform
+    const int nq = npad >> 5;
+    const int vo_yc = ((row0 >> 5) * 64 + lane) * 16;              // + (hb*nq + p) KB
+    const int vo_yr = ((row0 >> 5) * 2 * KS * 64 + lane) * 16;     // + ((2p + m) KS + ks) KB
 
     // One application of Q or Q^T to the register tile xr.  The correction
     // C = Y_slice W' of row group p (rows 32p + 8g + 4m + i, m = 0, 1) is
@@ -230,16 +295,29 @@ __global__ __launch_bounds__(kThreadsWY) void k_wy_fwd(WyArgs a) {
         for (int hb = 0; hb < HB; ++hb)
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) acc[hb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // A operands are fetched two row groups ahead of their use
+        constexpr int D1 = P < WY_DEPTH ? P : WY_DEPTH;
+        v8 abuf[D1][HB];
+#pragma unroll
+        for (int q = 0; q < D1; ++q)
+#pragma unroll
+            for (int hb = 0; hb < HB; ++hb)
+                abuf[q][hb] = bload<v8>(rYc, vo_yc, (hb * nq + q) * 1024);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             v8 av[HB];
 #pragma unroll
-            for (int hb = 0; hb < HB; ++hb)
-                av[hb] = bload<v8>(rYc, vo_yc + hb * 16 * npad * 2, 64 * p);
+            for (int hb = 0; hb < HB; ++hb) av[hb] = abuf[p % D1][hb];
+            if (p + D1 < P) {
+#pragma unroll
+                for (int hb = 0; hb < HB; ++hb)
+                    abuf[p % D1][hb] = bload<v8>(rYc, vo_yc, (hb * nq + p + D1) * 1024);
+            }
 #pragma unroll
             for (int hb = 0; hb < HB; ++hb)
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb) acc[hb][cb] = E::mfma(av[hb], xr[p][cb], acc[hb][cb]);
+            __builtin_amdgcn_sched_barrier(0);
         }
         // partials to LDS: element (h, col) of wave w
 #pragma unroll
@@ -248,14 +326,15 @@ __global__ __launch_bounds__(kThreadsWY) void k_wy_fwd(WyArgs a) {
             for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    sP[(w * HP + hb * 16 + 4 * g + i) * NB + cb * 16 + c] = acc[hb][cb][i];
+                    sP[(w * HP + hb * 16 + 4 * g + i) * NBP + cb * 16 + c] = acc[hb][cb][i];
         __syncthreads();
         // sum over waves (into wave 0's slot; each element has one owner)
         for (int e = tid; e < HP * NB; e += kThreadsWY) {
-            float s = sP[e];
+            const int ep = (e / NB) * NBP + e % NB;
+            float s = sP[ep];
 #pragma unroll
-            for (int v = 1; v < kWaves; ++v) s += sP[v * HP * NB + e];
-            sP[e] = s;
+            for (int v = 1; v < kWaves; ++v) s += sP[v * HP * NBP + ep];
+            sP[ep] = s;
         }
         __syncthreads();
         // W' = T W  (or T^T W), split into 16-bit hi + lo, stored as the GEMM2
@@ -265,12 +344,13 @@ __global__ __launch_bounds__(kThreadsWY) void k_wy_fwd(WyArgs a) {
             constexpr int RPP = kThreadsWY / TPR;       // rows per pass
             const int c4 = (tid % TPR) * 4;
             for (int i = tid / TPR; i < HP; i += RPP) {
+                // T is triangular; the zero half is multiplied too, which
+                // keeps the trip count fixed so the LDS reads pipeline.
                 f32x4 s = {0.f, 0.f, 0.f, 0.f};
-                const int kb = trans ? 0 : i;
-                const int ke = trans ? i + 1 : HP;
-                for (int k = kb; k < ke; ++k) {
-                    const float t = trans ? sT[k * HP + i] : sT[i * HP + k];
-                    const f32x4 wv = *reinterpret_cast<const f32x4 *>(sP + k * NB + c4);
+#pragma unroll 16
+                for (int k = 0; k < HP; ++k) {
+                    const float t = trans ? sT[k * HTP + i] : sT[i * HTP + k];
+                    const f32x4 wv = *reinterpret_cast<const f32x4 *>(sP + k * NBP + c4);
                     s += t * wv;
                 }
 #pragma unroll
@@ -278,30 +358,41 @@ __global__ __launch_bounds__(kThreadsWY) void k_wy_fwd(WyArgs a) {
                     const int col = c4 + q;
                     const el hi = (el)s[q];
                     const el lo = (el)(s[q] - (float)hi);
-                    sB[((0 * CB + col / 16) * 16 + col % 16) * HP + i] = hi;
-                    sB[((1 * CB + col / 16) * 16 + col % 16) * HP + i] = lo;
+                    sB[((0 * CB + col / 16) * 16 + col % 16) * HBP + i] = hi;
+                    sB[((1 * CB + col / 16) * 16 + col % 16) * HBP + i] = lo;
                 }
             }
         }
         __syncthreads();
-        v8 bfr[2][KS][CB];
-#pragma unroll
-        for (int hl = 0; hl < 2; ++hl)
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb)
-                    bfr[hl][ks][cb] = *reinterpret_cast<const v8 *>(
-                        sB + ((hl * CB + cb) * 16 + c) * HP + ks * 32 + 8 * g);
+        // W' fragments (GEMM2 B operand) are re-read from LDS at each use
+        auto bfrag = [&](int hl, int ks, int cb) {
+            return *reinterpret_cast<const v8 *>(sB + ((hl * CB + cb) * 16 + c) * HBP + ks * 32 + 8 * g);
+        };
         // GEMM2: correction C = Y_slice W' for every (p, m, cb)
+        constexpr int D2 = P < WY_DEPTH ? P : WY_DEPTH;
+        v8 bbuf[D2][2][KS];
+#pragma unroll
+        for (int q = 0; q < D2; ++q)
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks)
+                    bbuf[q][m][ks] = bload<v8>(rYr, vo_yr, ((2 * q + m) * KS + ks) * 1024);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             v8 av[2][KS];
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks)
-                    av[m][ks] = bload<v8>(rYr, vo_yr + (4 * m * HP + 32 * ks) * 2, 64 * HP * p);
+                for (int ks = 0; ks < KS; ++ks) av[m][ks] = bbuf[p % D2][m][ks];
+            if (p + D2 < P) {
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks)
+                        bbuf[p % D2][m][ks] =
+                            bload<v8>(rYr, vo_yr, ((2 * (p + D2) + m) * KS + ks) * 1024);
+            }
             f32x4 outc[2][CB];
 #pragma unroll
             for (int m = 0; m < 2; ++m)
@@ -310,41 +401,52 @@ __global__ __launch_bounds__(kThreadsWY) void k_wy_fwd(WyArgs a) {
                     f32x4 cc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                     for (int ks = 0; ks < KS; ++ks) {
-                        cc = E::mfma(av[m][ks], bfr[0][ks][cb], cc);
-                        cc = E::mfma(av[m][ks], bfr[1][ks][cb], cc);
+                        cc = E::mfma(av[m][ks], bfrag(0, ks, cb), cc);
+                        cc = E::mfma(av[m][ks], bfrag(1, ks, cb), cc);
                     }
                     outc[m][cb] = cc;
                 }
             consume(p, outc);
+            __builtin_amdgcn_sched_barrier(0);
         }
     };
 
     const int64_t ntiles = (a.N + NB - 1) / NB;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    auto tile_rsrc = [&](int64_t tile, const el *base, int64_t ld) {
         const int64_t col0 = tile * NB;
         const int64_t ncols = a.N - col0 < NB ? a.N - col0 : NB;
-        const __amdgpu_buffer_rsrc_t rX =
-            make_rsrc(X + col0 * a.ldx, (uint32_t)(((ncols - 1) * a.ldx + n) * 2));
-        const __amdgpu_buffer_rsrc_t rY =
-            make_rsrc(Yo + col0 * a.ldy, (uint32_t)(((ncols - 1) * a.ldy + n) * 2));
-        int vo_x[CB], vo_y[CB];
+        return make_rsrc(base + col0 * ld, (uint32_t)(((ncols - 1) * ld + n) * 2));
+    };
+    int vo_x[CB], vo_y[CB];
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            vo_x[cb] = (int)(((16 * cb + c) * a.ldx + row0 + 8 * g) * 2);
-            vo_y[cb] = (int)(((16 * cb + c) * a.ldy + row0 + 8 * g) * 2);
-        }
-        v8 xr[P][CB];
+    for (int cb = 0; cb < CB; ++cb) {
+        vo_x[cb] = (int)(((16 * cb + c) * a.ldx + row0 + 8 * g) * 2);
+        vo_y[cb] = (int)(((16 * cb + c) * a.ldy + row0 + 8 * g) * 2);
+    }
+    // X tile p-group load; rows at or past n read as zero
+    auto load_x = [&](__amdgpu_buffer_rsrc_t rX, int p, int cb) {
+        v8 v = bload<v8>(rX, vo_x[cb], 64 * p);
+        if (row0 + 32 * p + 8 * g >= n) v = v8{};
+        return v;
+    };
+    v8 xr[P][CB];
+    if ((int64_t)blockIdx.x < ntiles) {
+        const __amdgpu_buffer_rsrc_t rX0 = tile_rsrc(blockIdx.x, X, a.ldx);
 #pragma unroll
         for (int p = 0; p < P; ++p)
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                v8 v = bload<v8>(rX, vo_x[cb], 64 * p);
-                if (row0 + 32 * p + 8 * g >= n) v = v8{};
-                xr[p][cb] = v;
-            }
-        // y = x - C, rounded to the 16-bit type and stored
-        auto store_out = [&](int p, const f32x4(&cc)[2][CB]) {
-            const bool rok = row0 + 32 * p + 8 * g < n;
+            for (int cb = 0; cb < CB; ++cb) xr[p][cb] = load_x(rX0, p, cb);
+    }
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t next = tile + gridDim.x;
+        const bool has_next = next < ntiles;
+        const __amdgpu_buffer_rsrc_t rY = tile_rsrc(tile, Yo, a.ldy);
+        const __amdgpu_buffer_rsrc_t rXn = tile_rsrc(has_next ? next : tile, X, a.ldx);
+        // y = x - C, rounded to the 16-bit type, written back into the
+        // register tile.  No HBM access happens inside the GEMM loops: vmcnt
+        // retires in issue order, so a store or HBM load issued there would
+        // make every later L2 operand fetch wait for an HBM round trip.
+        auto keep_out = [&](int p, const f32x4(&cc)[2][CB]) {
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
                 v8 y;
@@ -353,7 +455,8 @@ __global__ __launch_bounds__(kThreadsWY) void k_wy_fwd(WyArgs a) {
                     y[j] = (el)((float)xr[p][cb][j] - cc[0][cb][j]);
                     y[j + 4] = (el)((float)xr[p][cb][j + 4] - cc[1][cb][j]);
                 }
-                if (rok) bstore<v8>(rY, y, vo_y[cb], 64 * p);
+                pin(y);
+                xr[p][cb] = y;
             }
         };
         if constexpr (OP == W_SYM) {
@@ -371,12 +474,26 @@ __global__ __launch_bounds__(kThreadsWY) void k_wy_fwd(WyArgs a) {
                         z[j] = (el)(((float)xr[p][cb][j] - cc[0][cb][j]) * l0[j]);
                         z[j + 4] = (el)(((float)xr[p][cb][j + 4] - cc[1][cb][j]) * l1[j]);
                     }
+                    pin(z);
                     xr[p][cb] = z;
                 }
             });
-            wy_pass(xr, false, store_out);
+            wy_pass(xr, false, keep_out);
         } else {
-            wy_pass(xr, OP == W_APPLY_T, store_out);
+            wy_pass(xr, OP == W_APPLY_T, keep_out);
+        }
+        // stores of this tile, then the next tile's loads into the same registers
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                if (row0 + 32 * p + 8 * g < n) bstore<v8>(rY, xr[p][cb], vo_y[cb], 64 * p);
+            }
+        if (has_next) {
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) xr[p][cb] = load_x(rXn, p, cb);
         }
     }
 }
@@ -392,13 +509,17 @@ bool wy_shape(int64_t n, int64_t h, WyShape *s) {
     s->hp = h <= 64 ? 64 : 128;
     s->p = n <= 1024 ? 4 : (n <= 4096 ? 16 : 32);
     s->cb = (s->p == 32 || s->hp == 128) ? 1 : 2;
+#ifdef WY_NB16
+    if (s->p == 16 && s->hp == 64) s->cb = 1;
+#endif
     s->npad = 256 * s->p;
     return true;
 }
 
 size_t wy_lds_bytes(const WyShape &s) {
-    const int nb = 16 * s.cb;
-    return (size_t)kWaves * s.hp * nb * 4 + (size_t)s.hp * s.hp * 4 + 2 * (size_t)nb * s.hp * 2;
+    const size_t nb = 16 * s.cb, hp = s.hp;
+    return kWaves * hp * (nb + 4) * 4 + ((hp * (hp + 1) + 3) & ~size_t(3)) * 4 +
+           2 * nb * (hp + 8) * 2;
 }
 
 struct WyWs {
@@ -427,11 +548,6 @@ __global__ void k_fill_lam(const float *__restrict__ lam, int n, int npad, float
     if (i < npad) out[i] = i < n ? lam[i] : 0.f;
 }
 
-__global__ void k_zero_f64(double *p, int64_t cnt) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < cnt) p[i] = 0.0;
-}
-
 template <typename E>
 hipError_t wy_setup(const WyShape &s, const float *U, int64_t ldu, int64_t n, int64_t h, char *ws,
                     const WyWs &w, bool want_uh, hipStream_t st) {
@@ -442,29 +558,28 @@ hipError_t wy_setup(const WyShape &s, const float *U, int64_t ldu, int64_t n, in
                        reinterpret_cast<double *>(ws + w.nrm2),
                        reinterpret_cast<double *>(ws + w.nrmraw),
                        want_uh ? reinterpret_cast<double *>(ws + w.uh64) : nullptr);
-    hipLaunchKernelGGL(k_zero_f64, dim3((hp * hp + 255) / 256), dim3(256), 0, st,
-                       reinterpret_cast<double *>(ws + w.gram), (int64_t)hp * hp);
     hipLaunchKernelGGL((k_wy_gram<E>), dim3(hp, hp), dim3(256), 0, st,
                        reinterpret_cast<const el *>(ws + w.yc), s.npad, hp,
                        reinterpret_cast<double *>(ws + w.gram));
-    hipLaunchKernelGGL(k_wy_tmat, dim3(1), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_wy_tmat, dim3(1), dim3(256), (size_t)hp * hp * 8, st,
                        reinterpret_cast<const double *>(ws + w.gram),
                        reinterpret_cast<const double *>(ws + w.nrm2), hp,
                        reinterpret_cast<double *>(ws + w.tw), reinterpret_cast<float *>(ws + w.tm));
     return hipGetLastError();
 }
 
-template <typename E, int P, int CB, int HP>
+template <typename E, int P, int CB, int HP, int MINB = 1>
 hipError_t launch_main(WyOp op, const WyArgs &a, size_t lds, int grid, hipStream_t st) {
+    grid *= MINB;
     switch (op) {
     case W_APPLY:
-        hipLaunchKernelGGL((k_wy_fwd<E, P, CB, HP, W_APPLY>), dim3(grid), dim3(kThreadsWY), lds, st, a);
+        hipLaunchKernelGGL((k_wy_fwd<E, P, CB, HP, W_APPLY, MINB>), dim3(grid), dim3(kThreadsWY), lds, st, a);
         break;
     case W_APPLY_T:
-        hipLaunchKernelGGL((k_wy_fwd<E, P, CB, HP, W_APPLY_T>), dim3(grid), dim3(kThreadsWY), lds, st, a);
+        hipLaunchKernelGGL((k_wy_fwd<E, P, CB, HP, W_APPLY_T, MINB>), dim3(grid), dim3(kThreadsWY), lds, st, a);
         break;
     case W_SYM:
-        hipLaunchKernelGGL((k_wy_fwd<E, P, CB, HP, W_SYM>), dim3(grid), dim3(kThreadsWY), lds, st, a);
+        hipLaunchKernelGGL((k_wy_fwd<E, P, CB, HP, W_SYM, MINB>), dim3(grid), dim3(kThreadsWY), lds, st, a);
         break;
     }
     return hipGetLastError();
@@ -478,7 +593,11 @@ hipError_t dispatch_main(const WyShape &s, WyOp op, const WyArgs &a, hipStream_t
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, device_cu_count()));
     if (s.hp == 64) {
         if (s.p == 4) return launch_main<E, 4, 2, 64>(op, a, lds, grid, st);
+#ifdef WY_NB16
+        if (s.p == 16) return launch_main<E, 16, 1, 64, 2>(op, a, lds, grid, st);
+#else
         if (s.p == 16) return launch_main<E, 16, 2, 64>(op, a, lds, grid, st);
+#endif
         return launch_main<E, 32, 1, 64>(op, a, lds, grid, st);
     }
     if (s.p == 4) return launch_main<E, 4, 1, 128>(op, a, lds, grid, st);
