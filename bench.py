@@ -46,6 +46,8 @@ WORKLOADS = {
                          "Mahalanobis forward + backward to U and lam, n=512, h=9, N=2^22; fused FP32"),
     "qx_n64_h4_f64": ("apply", 64, 4, 1024, "f64",
                       "Q X, n=64, h=4, N=1024; fused FP64"),
+    "copy_n4096_bf16": ("copy", 4096, 0, 1 << 18, "bf16",
+                        "device copy of the Q X batch (2 GiB in, 2 GiB out): HBM calibration"),
 }
 DEFAULT = "qx_n4096_h64"
 
@@ -58,6 +60,8 @@ def parse():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip timing the fused FP32 kernel beside the default workload")
     return ap.parse_args()
 
 
@@ -65,7 +69,7 @@ def algorithmic(op, n, h, N, io_bytes, param_bytes=4):
     """Bytes (one read of each input, one write of each output) and flops
     (operation counts of the paper: 4nh per Q x, (8h+1)n per symmetric
     product; (4h+3)n per distance) for one call over N vectors."""
-    if op == "apply":
+    if op in ("apply", "copy"):
         return 2 * n * io_bytes * N, 4 * n * h * N
     if op == "sym":
         return 2 * n * io_bytes * N, (8 * h + 1) * n * N
@@ -131,11 +135,13 @@ def main():
         Xb = synth.device_gaussian((N, n), seed=0, stream=synth.STREAM_XB, device=dev, dtype=io_dt)
     if op == "mahal_fb":
         w = synth.device_gaussian((N,), seed=0, stream=synth.STREAM_W, device=dev, dtype=pdt)
-    Y = torch.empty_like(X) if op in ("apply", "sym") else None
+    Y = torch.empty_like(X) if op in ("apply", "sym", "copy") else None
     torch.cuda.synchronize()
 
     def step():
-        if op == "apply":
+        if op == "copy":
+            Y.copy_(X)
+        elif op == "apply":
             P.apply_raw(U, X, compute=tdt, out=Y)
         elif op == "sym":
             P.sym_raw(U, lam, X, compute=tdt, out=Y)
@@ -203,8 +209,29 @@ def main():
                      "algorithmic_flops": aflops},
     }
 
+    # the fused FP32 kernel on the same Q X shape, timed beside the headline
+    if args.workload == DEFAULT and not args.no_compare:
+        del Y
+        Xf = X.float()
+        Yf = torch.empty_like(Xf)
+        for _ in range(1):
+            P.apply_raw(U, Xf, out=Yf)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        kf = max(1, min(args.steps, 5))
+        a.record(stream)
+        for _ in range(kf):
+            P.apply_raw(U, Xf, out=Yf)
+        b.record(stream)
+        torch.cuda.synchronize()
+        msf = a.elapsed_time(b) / kf
+        out["fused_f32"] = {"vectors_per_s": N / (msf * 1e-3), "ms_per_call": msf,
+                            "wy_speedup": (N / (ms_wall * 1e-3)) / (N / (msf * 1e-3))}
+        del Xf, Yf
+        Y = None
+
     # accuracy on a sample of vectors, and the oracle's own speed on it
-    if not args.no_cpu:
+    if not args.no_cpu and op != "copy":
         import oracle
         Uh = U.double().cpu().numpy()
         lh = lam.double().cpu().numpy()
@@ -237,7 +264,8 @@ def main():
                                "cores": oracle.num_threads(), "kind": "oracle",
                                "sample": f"first {S2} of {N} vectors of the same batch, FP64"}
         if op in ("apply", "sym"):
-            Yg = Y[:S].double().cpu().numpy()
+            Yg = (P.apply_raw(U, X[:S], compute=tdt) if op == "apply" else
+                  P.sym_raw(U, lam, X[:S], compute=tdt)).double().cpu().numpy()
             err = float(np.max(np.linalg.norm(Yg - ref, axis=1) / np.linalg.norm(ref, axis=1)))
         else:
             dg = P.mahal_raw(U, lam, X[:S], Xb[:S]).double().cpu().numpy()
