@@ -33,58 +33,17 @@
 #include <algorithm>
 #include <type_traits>
 
-#include "hh_wy.h"
+#include "hh_wy_common.h"
 
 namespace hh {
 namespace {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
-
 constexpr int kWaves = 8;
+constexpr int kThreadsWY = kWaves * kWave;
 #ifndef WY_DEPTH
 #define WY_DEPTH 3  // row groups of reflector operands fetched ahead of use
 #endif
-constexpr int kThreadsWY = kWaves * kWave;
 
-// 16-bit element types used on the matrix cores.
-struct BF16 {
-    typedef __bf16 elem;
-    typedef bf16x8 vec8;
-    static __device__ __forceinline__ f32x4 mfma(vec8 a, vec8 b, f32x4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-    }
-};
-struct F16 {
-    typedef _Float16 elem;
-    typedef f16x8 vec8;
-    static __device__ __forceinline__ f32x4 mfma(vec8 a, vec8 b, f32x4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-    }
-};
-
-enum WyOp { W_APPLY = 0, W_APPLY_T = 1, W_SYM = 2 };
-
-// ---------------------------------------------------------------------------
-// Fragment-ordered copies of the reflector matrix.  Every operand load of the
-// main kernel then reads one contiguous 1 KB block (64 lanes x 16 bytes).
-//   Yc (GEMM1 A operand, lane = (c, g)): element (h, row) with
-//     h = 16 hb + c, row = 32 q + 8 g + j  at  ((hb * NQ + q) * 64 + 16 g + c) * 8 + j
-//   Yr (GEMM2 A operand): element (h, row) with row = 32 q + 8 (c/4) + 4 m + c%4,
-//     h = 32 ks + 8 g + j  at  (((q * 2 + m) * KS + ks) * 64 + 16 g + c) * 8 + j
-// with NQ = npad / 32 and KS = hp / 32.
-__device__ __forceinline__ int64_t yc_index(int h, int row, int npad) {
-    const int hb = h >> 4, c = h & 15, q = row >> 5, g = (row >> 3) & 3, j = row & 7;
-    return ((int64_t)(hb * (npad >> 5) + q) * 64 + 16 * g + c) * 8 + j;
-}
-__device__ __forceinline__ int64_t yr_index(int h, int row, int hp) {
-    const int q = row >> 5, rr = row & 31;
-    const int c = 4 * (rr >> 3) + (rr & 3), m = (rr >> 2) & 1;
-    const int ks = h >> 5, g = (h >> 3) & 3, j = h & 7;
-    return ((int64_t)((q * 2 + m) * (hp >> 5) + ks) * 64 + 16 * g + c) * 8 + j;
-}
 
 // ---------------------------------------------------------------------------
 // Setup kernels (FP64).
@@ -210,42 +169,7 @@ __global__ __launch_bounds__(256) void k_wy_tmat(const double *__restrict__ G,
 
 // ---------------------------------------------------------------------------
 // Main kernel.
-struct WyArgs {
-    const void *X;
-    int64_t ldx;
-    void *Y;
-    int64_t ldy;
-    const void *Yc;   // HP x npad, column-major reflectors (GEMM1 A operand)
-    const void *Yr;   // npad x HP, row-major reflectors (GEMM2 A operand)
-    const float *Tm;  // HP x HP row-major
-    const float *lam; // npad (SYM)
-    int n, npad;
-    int64_t N;
-};
 
-// Raw buffer accesses: the base address lives in a scalar descriptor, the
-// lane part of the offset in one VGPR and the row-group part in an SGPR, so
-// the unrolled loops need no per-access 64-bit addresses.  Reads past
-// num_records return zero and writes past it are dropped.
-typedef int i32x4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
-}
-template <typename V>
-__device__ __forceinline__ V bload(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
-}
-// Forces v to be materialised here (an empty asm that reads and writes it),
-// so the optimiser cannot sink its computation towards a distant use.
-template <typename V> __device__ __forceinline__ void pin(V &v) { asm volatile("" : "+v"(v)); }
-
-template <typename V>
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, V v, int voff, int soff) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, v), r, voff, soff, 0);
-}
-
-// MINB blocks per CU: HIP's second launch-bounds argument is the minimum
-// number of waves per SIMD (2 per block of 8 waves).
 template <typename E, int P, int CB, int HP, int OP, int MINB>
 __global__ __launch_bounds__(kThreadsWY, 2 * MINB) void k_wy_fwd(WyArgs a) {
     using el = typename E::elem;
@@ -288,7 +212,8 @@ __global__ __launch_bounds__(kThreadsWY, 2 * MINB) void k_wy_fwd(WyArgs a) {
     // One application of Q or Q^T to the register tile xr.  The correction
     // C = Y_slice W' of row group p (rows 32p + 8g + 4m + i, m = 0, 1) is
     // handed to consume(p, cc) as soon as it is formed.
-    auto wy_pass = [&](v8(&xr)[P][CB], bool trans, auto &&consume) {
+    auto wy_pass = [&](v8(&xr)[P][CB], bool trans, int pass, int64_t col0, bool gemm2,
+                       auto &&consume) {
         // GEMM1: per-wave partial W = Y_slice^T X_slice.
         f32x4 acc[HB][CB];
 #pragma unroll
@@ -296,7 +221,8 @@ __global__ __launch_bounds__(kThreadsWY, 2 * MINB) void k_wy_fwd(WyArgs a) {
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) acc[hb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
         // A operands are fetched two row groups ahead of their use
-        constexpr int D1 = P < WY_DEPTH ? P : WY_DEPTH;
+        constexpr int DW1 = HB >= 8 ? 1 : WY_DEPTH;  // fewer stages for wide operands
+        constexpr int D1 = P < DW1 ? P : DW1;
         v8 abuf[D1][HB];
 #pragma unroll
         for (int q = 0; q < D1; ++q)
@@ -361,15 +287,23 @@ __global__ __launch_bounds__(kThreadsWY, 2 * MINB) void k_wy_fwd(WyArgs a) {
                     sB[((0 * CB + col / 16) * 16 + col % 16) * HBP + i] = hi;
                     sB[((1 * CB + col / 16) * 16 + col % 16) * HBP + i] = lo;
                 }
+                if (a.coef) {  // coefficients for the backward pass, 16-bit
+                    el *cp = static_cast<el *>(a.coef) + (int64_t)(pass * HP + i) * a.ldc + col0 + c4;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (col0 + c4 + q < a.N) cp[q] = (el)s[q];
+                }
             }
         }
         __syncthreads();
+        if (!gemm2) return;
         // W' fragments (GEMM2 B operand) are re-read from LDS at each use
         auto bfrag = [&](int hl, int ks, int cb) {
             return *reinterpret_cast<const v8 *>(sB + ((hl * CB + cb) * 16 + c) * HBP + ks * 32 + 8 * g);
         };
         // GEMM2: correction C = Y_slice W' for every (p, m, cb)
-        constexpr int D2 = P < WY_DEPTH ? P : WY_DEPTH;
+        constexpr int DW2 = KS >= 4 ? 1 : WY_DEPTH;
+        constexpr int D2 = P < DW2 ? P : DW2;
         v8 bbuf[D2][2][KS];
 #pragma unroll
         for (int q = 0; q < D2; ++q)
@@ -438,6 +372,7 @@ __global__ __launch_bounds__(kThreadsWY, 2 * MINB) void k_wy_fwd(WyArgs a) {
             for (int cb = 0; cb < CB; ++cb) xr[p][cb] = load_x(rX0, p, cb);
     }
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t col0 = tile * NB;
         const int64_t next = tile + gridDim.x;
         const bool has_next = next < ntiles;
         const __amdgpu_buffer_rsrc_t rY = tile_rsrc(tile, Yo, a.ldy);
@@ -463,7 +398,7 @@ __global__ __launch_bounds__(kThreadsWY, 2 * MINB) void k_wy_fwd(WyArgs a) {
             // z = lam .* (x - C), rounded back into the register tile
             const __amdgpu_buffer_rsrc_t rL = make_rsrc(a.lam, (uint32_t)npad * 4);
             const int vo_l = (row0 + 8 * g) * 4;
-            wy_pass(xr, true, [&](int p, const f32x4(&cc)[2][CB]) {
+            wy_pass(xr, true, 0, col0, true, [&](int p, const f32x4(&cc)[2][CB]) {
                 const f32x4 l0 = bload<f32x4>(rL, vo_l, 128 * p);
                 const f32x4 l1 = bload<f32x4>(rL, vo_l + 16, 128 * p);
 #pragma unroll
@@ -478,17 +413,19 @@ __global__ __launch_bounds__(kThreadsWY, 2 * MINB) void k_wy_fwd(WyArgs a) {
                     xr[p][cb] = z;
                 }
             });
-            wy_pass(xr, false, keep_out);
+            wy_pass(xr, false, 1, col0, a.store != 0, keep_out);
         } else {
-            wy_pass(xr, OP == W_APPLY_T, keep_out);
+            wy_pass(xr, OP == W_APPLY_T, 0, col0, a.store != 0, keep_out);
         }
         // stores of this tile, then the next tile's loads into the same registers
+        if (a.store) {
 #pragma unroll
-        for (int p = 0; p < P; ++p)
+            for (int p = 0; p < P; ++p)
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                if (row0 + 32 * p + 8 * g < n) bstore<v8>(rY, xr[p][cb], vo_y[cb], 64 * p);
-            }
+                for (int cb = 0; cb < CB; ++cb) {
+                    if (row0 + 32 * p + 8 * g < n) bstore<v8>(rY, xr[p][cb], vo_y[cb], 64 * p);
+                }
+        }
         if (has_next) {
 #pragma unroll
             for (int p = 0; p < P; ++p)
@@ -500,47 +437,10 @@ __global__ __launch_bounds__(kThreadsWY, 2 * MINB) void k_wy_fwd(WyArgs a) {
 
 // ---------------------------------------------------------------------------
 // Host side.
-struct WyShape {
-    int hp, p, cb, npad;
-};
-
-bool wy_shape(int64_t n, int64_t h, WyShape *s) {
-    if (h > 128 || n > 8192) return false;
-    s->hp = h <= 64 ? 64 : 128;
-    s->p = n <= 1024 ? 4 : (n <= 4096 ? 16 : 32);
-    s->cb = (s->p == 32 || s->hp == 128) ? 1 : 2;
-#ifdef WY_NB16
-    if (s->p == 16 && s->hp == 64) s->cb = 1;
-#endif
-    s->npad = 256 * s->p;
-    return true;
-}
-
 size_t wy_lds_bytes(const WyShape &s) {
     const size_t nb = 16 * s.cb, hp = s.hp;
     return kWaves * hp * (nb + 4) * 4 + ((hp * (hp + 1) + 3) & ~size_t(3)) * 4 +
            2 * nb * (hp + 8) * 2;
-}
-
-struct WyWs {
-    size_t yc, yr, nrm2, nrmraw, gram, tw, tm, lam, uh64, total;
-};
-
-WyWs wy_ws(const WyShape &s, int64_t n, bool with_lam, bool bwd) {
-    WyWs w{};
-    size_t off = 0;
-    const size_t hp = s.hp, np = s.npad;
-    w.yc = off;     off += align256(hp * np * 2);
-    w.yr = off;     off += align256(hp * np * 2);
-    w.nrm2 = off;   off += align256(hp * 8);
-    w.nrmraw = off; off += align256(hp * 8);
-    w.gram = off;   off += align256(hp * hp * 8);
-    w.tw = off;     off += align256(hp * hp * 8);
-    w.tm = off;     off += align256(hp * hp * 4);
-    w.lam = off;    off += with_lam ? align256(np * 4) : 0;
-    w.uh64 = off;   off += bwd ? align256(hp * (size_t)n * 8) : 0;
-    w.total = off;
-    return w;
 }
 
 __global__ void k_fill_lam(const float *__restrict__ lam, int n, int npad, float *__restrict__ out) {
@@ -593,11 +493,7 @@ hipError_t dispatch_main(const WyShape &s, WyOp op, const WyArgs &a, hipStream_t
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, device_cu_count()));
     if (s.hp == 64) {
         if (s.p == 4) return launch_main<E, 4, 2, 64>(op, a, lds, grid, st);
-#ifdef WY_NB16
-        if (s.p == 16) return launch_main<E, 16, 1, 64, 2>(op, a, lds, grid, st);
-#else
         if (s.p == 16) return launch_main<E, 16, 2, 64>(op, a, lds, grid, st);
-#endif
         return launch_main<E, 32, 1, 64>(op, a, lds, grid, st);
     }
     if (s.p == 4) return launch_main<E, 4, 1, 128>(op, a, lds, grid, st);
@@ -607,12 +503,32 @@ hipError_t dispatch_main(const WyShape &s, WyOp op, const WyArgs &a, hipStream_t
 
 }  // namespace
 
+hipError_t wy_setup_any(bool bf, const WyShape &s, const float *U, int64_t ldu, int64_t n,
+                        int64_t h, char *ws, const WyWs &w, bool want_uh, hipStream_t st) {
+    return bf ? wy_setup<BF16>(s, U, ldu, n, h, ws, w, want_uh, st)
+              : wy_setup<F16>(s, U, ldu, n, h, ws, w, want_uh, st);
+}
+
+hipError_t wy_fill_lam(const float *lam, int n, int npad, float *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_lam, dim3((npad + 255) / 256), dim3(256), 0, st, lam, n, npad, out);
+    return hipGetLastError();
+}
+
+hipError_t wy_main_any(bool bf, const WyShape &s, WyOp op, const WyArgs &a, hipStream_t st) {
+    if (a.N == 0) return hipSuccess;
+    return bf ? dispatch_main<BF16>(s, op, a, st) : dispatch_main<F16>(s, op, a, st);
+}
+
 hh_status wy_workspace_size(hh_op op, const hh_desc *d, size_t *bytes) {
     WyShape s;
     if (!wy_shape(d->n, d->h, &s))
         return set_error(HH_ERR_UNSUPPORTED, "WY path supports n <= 8192 and h <= 128");
-    if (op == HH_OP_MAHAL || op >= HH_OP_APPLY_BWD)
+    if (op == HH_OP_MAHAL || op == HH_OP_MAHAL_BWD)
         return set_error(HH_ERR_UNSUPPORTED, "WY path provides Q X, Q^T X and Q diag(lam) Q^T X");
+    if (op >= HH_OP_APPLY_BWD) {
+        *bytes = wy_bwd_ws_bytes(op, s, d->n, d->N);
+        return HH_OK;
+    }
     *bytes = wy_ws(s, d->n, op == HH_OP_SYM, false).total;
     return HH_OK;
 }
@@ -661,6 +577,7 @@ hh_status wy_forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, con
     a.Yr = base + w.yr;
     a.Tm = reinterpret_cast<const float *>(base + w.tm);
     a.lam = reinterpret_cast<const float *>(base + w.lam);
+    a.store = 1;
     a.n = (int)n;
     a.npad = s.npad;
     a.N = N;
@@ -668,12 +585,6 @@ hh_status wy_forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, con
     e = bf ? dispatch_main<BF16>(s, wop, a, st) : dispatch_main<F16>(s, wop, a, st);
     if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY kernel launch: %s", hipGetErrorString(e));
     return HH_OK;
-}
-
-hh_status wy_backward(hh_op, const hh_desc *, const void *, int64_t, const void *, const void *,
-                      int64_t, const void *, int64_t, const void *, int64_t, void *, void *,
-                      int64_t, void *, int64_t, void *, void *, size_t, hipStream_t) {
-    return set_error(HH_ERR_UNSUPPORTED, "WY backward not built yet");
 }
 
 }  // namespace hh

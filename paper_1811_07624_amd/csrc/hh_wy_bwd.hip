@@ -1,0 +1,557 @@
+// Backward of the compact-WY path (BF16 / FP16 on the matrix cores).
+//
+// With coefficients scaled by tau (a_k = tau_k y_k^T s_{k-1}, b_k = tau_k y_k^T g_k)
+// the chain rule of one reflector chain sums, over the N vectors, to
+//   dL/dY = -(G_end A^T + S_0 B^T) + Y C,   C = h x h triangular parts of B A^T
+// (the order of the chain decides which triangle; see the combine step).  The
+// coefficient matrices are exactly what the WY products compute: for Q X,
+// A = T Y^T X and B = T^T Y^T G; for Q^T X the transposes of T swap.  For the
+// symmetric form, substituting Q^T G = G - Y B2 and Q^T X = X - Y A1 leaves only
+// the inputs X and G in the large products:
+//   dL/dY = -diag(lam) (G A1^T + X B2^T) - (G A2^T + X B1^T)
+//           + diag(lam) Y (K1 + K1^T) + Y (stril K2 + striu K2^T + striu K3 + stril K3^T)
+//   dlam_i = sum_j G_ij X_ij - sum_k Y_ik (G A1^T + X B2^T)_ik + sum_k (Y K1)_ik Y_ik
+// with K1 = B2 A1^T, K2 = B1 A1^T, K3 = B2 A2^T (A1 = T^T Y^T X, A2 = T Y^T lam Q^T X,
+// B2 = T^T Y^T G, B1 = T Y^T lam Q^T G).
+//
+// Steps (all on the caller's stream): setup; a WY pass over X that only emits
+// A; a WY pass over G that emits B and writes dX (= Q^T G, Q G or S G); one
+// rank-N product out = G [A..]^T + X [B..]^T on MFMA with the reduction over
+// vectors split across blocks; coefficient Grams on MFMA; then FP64 sums of
+// the block partials, the small h x h terms, and the chain rule of the
+// normalisation dU = (I - uh uh^T) dL/duh / ||u||.  Partials are summed in a
+// fixed order: the result is deterministic for a given device and shape.
+#include <algorithm>
+
+#include "hh_wy_common.h"
+
+namespace hh {
+namespace {
+
+constexpr int kT = 512;  // threads of the product kernels
+
+struct RankArgs {
+    const void *D[2];   // G, X (n x N, 16-bit, column-major)
+    int64_t ld[2];
+    const void *C[2];   // coefficients for G and for X (m x ldc, 16-bit, row-major in j)
+    int64_t ldc;
+    float *out;         // [KS][npad][m]
+    float *gx;          // nullable: [KS][2][npad]
+    int n, npad;
+    int64_t N, chunk;
+};
+
+// out[s][r][m] = sum over the vectors j of split s of G[r][j] C0[m][j] + X[r][j] C1[m][j].
+// Block: rows [256 bx, 256 bx + 256), wave w owns 32 of them, all m columns.
+template <typename E, int MB>
+__global__ __launch_bounds__(kT) void k_wy_rank(RankArgs a) {
+    using el = typename E::elem;
+    using v8 = typename E::vec8;
+    constexpr int M = 16 * MB;
+    constexpr int RS = 256 + 4;   // LDS row stride of a staged vector slice (elements)
+    constexpr int CSd = 32 + 8;   // LDS row stride of a staged coefficient row
+    constexpr int CD = 4;         // 16-byte data chunks per thread per step
+    constexpr int CC = (2 * M * 4 + kT - 1) / kT;
+    extern __shared__ __align__(16) unsigned char smem[];
+    el *sD = reinterpret_cast<el *>(smem);      // [2][32][RS]
+    el *sC = sD + 2 * 32 * RS;                  // [2][M][CSd]
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6, c = lane & 15, g = lane >> 4;
+    const int rb0 = blockIdx.x * 256;
+    const int64_t jb = (int64_t)blockIdx.y * a.chunk;
+    const int64_t je = jb + a.chunk < a.N ? jb + a.chunk : a.N;
+    const el *D0 = static_cast<const el *>(a.D[0]);
+    const el *D1 = static_cast<const el *>(a.D[1]);
+    const el *C0 = static_cast<const el *>(a.C[0]);
+    const el *C1 = static_cast<const el *>(a.C[1]);
+
+    f32x4 acc[2][MB];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[r][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float gxa = 0.f;
+
+    v8 rd[CD], rc[CC];
+    auto load_step = [&](int64_t j0) {
+#pragma unroll
+        for (int t = 0; t < CD; ++t) {
+            const int ci = tid + kT * t;
+            const int src = ci >> 10, cc = ci & 1023, j = cc >> 5, rcn = cc & 31;
+            const int row = rb0 + 8 * rcn;
+            const int64_t jj = j0 + j;
+            v8 v = {};
+            if (jj < je && row < a.n) {
+                const el *Dp = src ? D1 : D0;
+                v = *reinterpret_cast<const v8 *>(Dp + jj * a.ld[src] + row);
+            }
+            rd[t] = v;
+        }
+#pragma unroll
+        for (int t = 0; t < CC; ++t) {
+            const int ci = tid + kT * t;
+            v8 v = {};
+            if (ci < 2 * M * 4) {
+                const int src = ci / (M * 4), cc = ci % (M * 4), mr = cc >> 2, jc = cc & 3;
+                if (j0 + 8 * jc < je) {
+                    const el *Cp = src ? C1 : C0;
+                    v = *reinterpret_cast<const v8 *>(Cp + (int64_t)mr * a.ldc + j0 + 8 * jc);
+                }
+            }
+            rc[t] = v;
+        }
+    };
+    auto store_step = [&]() {
+#pragma unroll
+        for (int t = 0; t < CD; ++t) {
+            const int ci = tid + kT * t;
+            const int src = ci >> 10, cc = ci & 1023, j = cc >> 5, rcn = cc & 31;
+            typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+            const u64x2 b = __builtin_bit_cast(u64x2, rd[t]);
+            unsigned long long *dst =
+                reinterpret_cast<unsigned long long *>(sD + (src * 32 + j) * RS + 8 * rcn);
+            dst[0] = b[0];
+            dst[1] = b[1];
+        }
+#pragma unroll
+        for (int t = 0; t < CC; ++t) {
+            const int ci = tid + kT * t;
+            if (ci < 2 * M * 4) {
+                const int src = ci / (M * 4), cc = ci % (M * 4), mr = cc >> 2, jc = cc & 3;
+                *reinterpret_cast<v8 *>(sC + (src * M + mr) * CSd + 8 * jc) = rc[t];
+            }
+        }
+    };
+
+    if (jb < je) load_step(jb);
+    for (int64_t j0 = jb; j0 < je; j0 += 32) {
+        __syncthreads();
+        store_step();
+        __syncthreads();
+        if (j0 + 32 < je) load_step(j0 + 32);
+#pragma unroll
+        for (int src = 0; src < 2; ++src) {
+            v8 bfr[2];
+#pragma unroll
+            for (int rbk = 0; rbk < 2; ++rbk)
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    bfr[rbk][q] = sD[(src * 32 + 8 * g + q) * RS + 32 * w + 16 * rbk + c];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const v8 afr = *reinterpret_cast<const v8 *>(sC + (src * M + 16 * mb + c) * CSd + 8 * g);
+#pragma unroll
+                for (int rbk = 0; rbk < 2; ++rbk) acc[rbk][mb] = E::mfma(afr, bfr[rbk], acc[rbk][mb]);
+            }
+        }
+        if (a.gx) {
+            const int row = tid & 255, half = tid >> 8;
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                gxa += (float)sD[(16 * half + j) * RS + row] * (float)sD[(32 + 16 * half + j) * RS + row];
+        }
+    }
+#pragma unroll
+    for (int rbk = 0; rbk < 2; ++rbk) {
+        const int r = rb0 + 32 * w + 16 * rbk + c;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+            *reinterpret_cast<f32x4 *>(a.out + ((size_t)blockIdx.y * a.npad + r) * M + 16 * mb + 4 * g) =
+                acc[rbk][mb];
+    }
+    if (a.gx) a.gx[((size_t)blockIdx.y * 2 + (tid >> 8)) * a.npad + rb0 + (tid & 255)] = gxa;
+}
+
+struct GramArgs {
+    const void *P[3], *Q[3];  // coefficient rows (HP x ldc, 16-bit)
+    int64_t ldc;
+    float *out;               // [pairs][KSg][HP][HP]
+    int64_t N, chunk;
+};
+
+// out[pair][s][k][l] = sum over the vectors j of split s of P[k][j] Q[l][j].
+template <typename E, int HB>
+__global__ __launch_bounds__(kT) void k_wy_cgram(GramArgs a) {
+    using el = typename E::elem;
+    using v8 = typename E::vec8;
+    constexpr int HP = 16 * HB;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6, c = lane & 15, g = lane >> 4;
+    const int pair = blockIdx.y;
+    const int64_t jb = (int64_t)blockIdx.x * a.chunk;
+    const int64_t je = jb + a.chunk < a.N ? jb + a.chunk : a.N;
+    const el *Pm = static_cast<const el *>(a.P[pair]);
+    const el *Qm = static_cast<const el *>(a.Q[pair]);
+    for (int kb = w; kb < HB; kb += kT / 64) {
+        f32x4 acc[HB];
+#pragma unroll
+        for (int lb = 0; lb < HB; ++lb) acc[lb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int64_t j0 = jb; j0 < je; j0 += 32) {
+            // pad columns past N are zero in the coefficient buffers
+            const v8 afr = *reinterpret_cast<const v8 *>(Pm + (int64_t)(16 * kb + c) * a.ldc + j0 + 8 * g);
+#pragma unroll
+            for (int lb = 0; lb < HB; ++lb) {
+                const v8 bfr = *reinterpret_cast<const v8 *>(Qm + (int64_t)(16 * lb + c) * a.ldc + j0 + 8 * g);
+                acc[lb] = E::mfma(afr, bfr, acc[lb]);
+            }
+        }
+        float *o = a.out + ((size_t)pair * gridDim.x + blockIdx.x) * HP * HP;
+#pragma unroll
+        for (int lb = 0; lb < HB; ++lb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o[(16 * kb + 4 * g + i) * HP + 16 * lb + c] = acc[lb][i];
+    }
+}
+
+// Zero the columns [N, ldc) of an m x ldc coefficient buffer.
+template <typename T>
+__global__ void k_zero_cols(T *p, int m, int64_t N, int64_t ldc) {
+    const int64_t pad = ldc - N;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < (int64_t)m * pad) p[(i / pad) * ldc + N + i % pad] = (T)0;
+}
+
+// K[pair][e] = sum over splits (FP64, fixed order); then the h x h matrices the
+// combine step needs, stored transposed (Mt[k][l] = M[l][k]):
+//   Ma = K1 + K1^T (symmetric form only), Mb = the order-dependent triangles,
+//   Mc = K1 (symmetric form only).
+__global__ __launch_bounds__(256) void k_wy_mmat(const float *__restrict__ part, int ksg, int hp,
+                                                int kind, double *__restrict__ Kd,
+                                                double *__restrict__ Ma, double *__restrict__ Mb,
+                                                double *__restrict__ Mc) {
+    const int npairs = kind == 2 ? 3 : 1;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= hp * hp) return;
+    for (int pr = 0; pr < npairs; ++pr) {
+        double s = 0.0;
+        for (int q = 0; q < ksg; ++q) s += (double)part[((size_t)pr * ksg + q) * hp * hp + e];
+        Kd[(size_t)pr * hp * hp + e] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_wy_mmat2(const double *__restrict__ Kd, int hp, int kind,
+                                                 double *__restrict__ Ma, double *__restrict__ Mb,
+                                                 double *__restrict__ Mc) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= hp * hp) return;
+    const int k = e / hp, l = e % hp;  // Mt[k][l] = M[l][k]
+    auto K = [&](int pr, int i, int j) { return Kd[(size_t)pr * hp * hp + i * hp + j]; };
+    double mb = 0.0;
+    if (kind == 0) {         // Q X: chain visits k = h..1 -> striu(K) + stril(K^T)
+        mb = (l < k ? K(0, l, k) : 0.0) + (l > k ? K(0, k, l) : 0.0);
+    } else if (kind == 1) {  // Q^T X: chain visits k = 1..h -> stril(K) + striu(K^T)
+        mb = (l > k ? K(0, l, k) : 0.0) + (l < k ? K(0, k, l) : 0.0);
+    } else {                 // symmetric form
+        mb = (l > k ? K(1, l, k) : 0.0) + (l < k ? K(1, k, l) : 0.0) +
+             (l < k ? K(2, l, k) : 0.0) + (l > k ? K(2, k, l) : 0.0);
+        Ma[e] = K(0, l, k) + K(0, k, l);
+        Mc[e] = K(0, l, k);
+    }
+    Mb[e] = mb;
+}
+
+struct CombineArgs {
+    const float *part;   // [KS][npad][m]
+    const float *gx;     // nullable [KS][2][npad]
+    int ks, m;
+    const double *uh;    // h x n, FP64 unit reflectors
+    const double *Ma, *Mb, *Mc;  // transposed hp x hp
+    const float *lam;    // padded spectrum (symmetric form)
+    double *dV;          // hp x npad
+    float *dlam;         // nullable, n
+    int n, h, hp, npad, kind;
+};
+
+// One block per row r, one thread per reflector k (blockDim = hp).
+__global__ __launch_bounds__(128) void k_wy_combine(CombineArgs a) {
+    __shared__ double yr[128];
+    __shared__ double red[128];
+    const int r = blockIdx.x;
+    const int k = threadIdx.x;
+    const int hp = a.hp;
+    yr[k] = (k < a.h && r < a.n) ? a.uh[(size_t)k * a.n + r] : 0.0;
+    __syncthreads();
+    double o1 = 0.0, o2 = 0.0;
+    for (int s = 0; s < a.ks; ++s) {
+        const float *row = a.part + ((size_t)s * a.npad + r) * a.m;
+        o1 += (double)row[k];
+        if (a.kind == 2) o2 += (double)row[hp + k];
+    }
+    double yb = 0.0, ya = 0.0, yc = 0.0;
+    for (int l = 0; l < hp; ++l) {
+        const double y = yr[l];
+        yb += y * a.Mb[(size_t)k * hp + l];
+        if (a.kind == 2) {
+            ya += y * a.Ma[(size_t)k * hp + l];
+            yc += y * a.Mc[(size_t)k * hp + l];
+        }
+    }
+    double dv, contrib = 0.0;
+    if (a.kind == 2) {
+        const double lr = (r < a.n) ? (double)a.lam[r] : 0.0;
+        dv = -lr * o1 - o2 + lr * ya + yb;
+        contrib = -yr[k] * o1 + yc * yr[k];
+    } else {
+        dv = -o1 + yb;
+    }
+    a.dV[(size_t)k * a.npad + r] = dv;
+    if (a.kind == 2 && a.dlam) {
+        red[k] = contrib;
+        __syncthreads();
+        for (int q = hp / 2; q > 0; q >>= 1) {
+            if (k < q) red[k] += red[k + q];
+            __syncthreads();
+        }
+        if (k == 0 && r < a.n) {
+            double gx = 0.0;
+            if (a.gx)
+                for (int s = 0; s < 2 * a.ks; ++s) gx += (double)a.gx[(size_t)s * a.npad + r];
+            a.dlam[r] = (float)(gx + red[0]);
+        }
+    }
+}
+
+// dU_k = (I - uh_k uh_k^T) dV_k / ||u_k||, one block per reflector.
+__global__ __launch_bounds__(256) void k_wy_finish(const double *__restrict__ dV, int npad, int n,
+                                                  const double *__restrict__ uh,
+                                                  const double *__restrict__ nrm, float *__restrict__ dU,
+                                                  int64_t lddu) {
+    __shared__ double red[256];
+    const int k = blockIdx.x;
+    const int t = threadIdx.x;
+    const double *v = dV + (size_t)k * npad;
+    const double *u = uh + (size_t)k * n;
+    double p = 0.0;
+    for (int e = t; e < n; e += 256) p += u[e] * v[e];
+    red[t] = p;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    p = red[0];
+    const double nk = nrm[k];
+    for (int e = t; e < n; e += 256) dU[e + (int64_t)k * lddu] = nk > 0.0 ? (float)((v[e] - p * u[e]) / nk) : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+struct BwdLayout {
+    WyWs base;
+    int64_t ldc;
+    int m, ks, ksg, npairs;
+    int64_t chunk, gchunk;
+    size_t cg, cx, part, gx, gpart, kd, ma, mb, mc, dv, total;
+};
+
+BwdLayout bwd_layout(hh_op op, const WyShape &s, int64_t n, int64_t N) {
+    BwdLayout L{};
+    const bool sym = op == HH_OP_SYM_BWD;
+    L.base = wy_ws(s, n, sym, true);
+    L.ldc = std::max<int64_t>(32, (N + 31) / 32 * 32);
+    L.m = sym ? 2 * s.hp : s.hp;
+    const int rowblocks = s.npad / 256;
+    const int64_t steps = std::max<int64_t>(1, (N + 31) / 32);
+    L.ks = (int)std::min<int64_t>(steps, std::max(1, 2 * device_cu_count() / rowblocks));
+    L.chunk = (steps + L.ks - 1) / L.ks * 32;
+    L.ks = (int)std::max<int64_t>(1, (N + L.chunk - 1) / L.chunk);
+    L.npairs = sym ? 3 : 1;
+    L.ksg = (int)std::min<int64_t>(steps, 128);
+    L.gchunk = (steps + L.ksg - 1) / L.ksg * 32;
+    L.ksg = (int)std::max<int64_t>(1, (N + L.gchunk - 1) / L.gchunk);
+    const size_t hp = s.hp;
+    size_t off = L.base.total;
+    L.cg = off;    off += align256((size_t)L.m * L.ldc * 2);
+    L.cx = off;    off += align256((size_t)L.m * L.ldc * 2);
+    L.part = off;  off += align256((size_t)L.ks * s.npad * L.m * 4);
+    L.gx = off;    off += sym ? align256((size_t)L.ks * 2 * s.npad * 4) : 0;
+    L.gpart = off; off += align256((size_t)L.npairs * L.ksg * hp * hp * 4);
+    L.kd = off;    off += align256((size_t)L.npairs * hp * hp * 8);
+    L.ma = off;    off += align256(hp * hp * 8);
+    L.mb = off;    off += align256(hp * hp * 8);
+    L.mc = off;    off += align256(hp * hp * 8);
+    L.dv = off;    off += align256(hp * (size_t)s.npad * 8);
+    L.total = off;
+    return L;
+}
+
+template <typename E>
+hipError_t launch_products(const WyShape &s, const BwdLayout &L, char *ws, const void *G,
+                           int64_t ldg, const void *X, int64_t ldx, int64_t N, int n, bool sym,
+                           hipStream_t st) {
+    RankArgs ra{};
+    ra.D[0] = G;
+    ra.ld[0] = ldg;
+    ra.D[1] = X;
+    ra.ld[1] = ldx;
+    ra.C[0] = ws + L.cg;
+    ra.C[1] = ws + L.cx;
+    ra.ldc = L.ldc;
+    ra.out = reinterpret_cast<float *>(ws + L.part);
+    ra.gx = sym ? reinterpret_cast<float *>(ws + L.gx) : nullptr;
+    ra.n = n;
+    ra.npad = s.npad;
+    ra.N = N;
+    ra.chunk = L.chunk;
+    const dim3 rgrid(s.npad / 256, L.ks);
+    const size_t rlds = (size_t)(2 * 32 * (256 + 4) + 2 * L.m * (32 + 8)) * 2;
+    switch (L.m) {
+    case 64: hipLaunchKernelGGL((k_wy_rank<E, 4>), rgrid, dim3(kT), rlds, st, ra); break;
+    case 128: hipLaunchKernelGGL((k_wy_rank<E, 8>), rgrid, dim3(kT), rlds, st, ra); break;
+    default: hipLaunchKernelGGL((k_wy_rank<E, 16>), rgrid, dim3(kT), rlds, st, ra); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    GramArgs ga{};
+    const size_t hpb = (size_t)s.hp * L.ldc * 2;  // bytes of HP coefficient rows
+    char *cg = ws + L.cg, *cx = ws + L.cx;
+    if (sym) {  // K1 = B2 A1^T, K2 = B1 A1^T, K3 = B2 A2^T
+        ga.P[0] = cx; ga.Q[0] = cg;
+        ga.P[1] = cx + hpb; ga.Q[1] = cg;
+        ga.P[2] = cx; ga.Q[2] = cg + hpb;
+    } else {    // K = B A^T
+        ga.P[0] = cx; ga.Q[0] = cg;
+    }
+    ga.ldc = L.ldc;
+    ga.out = reinterpret_cast<float *>(ws + L.gpart);
+    ga.N = N;
+    ga.chunk = L.gchunk;
+    const dim3 ggrid(L.ksg, L.npairs);
+    if (s.hp == 64) hipLaunchKernelGGL((k_wy_cgram<E, 4>), ggrid, dim3(kT), 0, st, ga);
+    else hipLaunchKernelGGL((k_wy_cgram<E, 8>), ggrid, dim3(kT), 0, st, ga);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t wy_bwd_ws_bytes(hh_op op, const WyShape &s, int64_t n, int64_t N) {
+    return bwd_layout(op, s, n, N).total;
+}
+
+hh_status wy_backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, const void *lam,
+                      const void *X, int64_t ldx, const void *Xb, int64_t ldb, const void *G,
+                      int64_t ldg, void *dX, void *dXb, int64_t lddx, void *dU, int64_t lddu,
+                      void *dlam, void *ws, size_t ws_bytes, hipStream_t st) {
+    (void)Xb;
+    (void)ldb;
+    (void)dXb;
+    WyShape s;
+    if (!wy_shape(d->n, d->h, &s))
+        return set_error(HH_ERR_UNSUPPORTED, "WY path supports n <= 8192 and h <= 128");
+    if (op == HH_OP_MAHAL_BWD)
+        return set_error(HH_ERR_UNSUPPORTED, "WY path provides Q X, Q^T X and Q diag(lam) Q^T X");
+    if (d->io_dtype != d->compute_dtype)
+        return set_error(HH_ERR_UNSUPPORTED, "WY path reads and writes data in the compute type");
+    const int64_t n = d->n, h = d->h, N = d->N;
+    const bool sym = op == HH_OP_SYM_BWD;
+    auto al16 = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+    if (n % 8 != 0 || ldx % 8 != 0 || ldg % 8 != 0 || (dX && lddx % 8 != 0) ||
+        (N > 0 && (!al16(X) || !al16(G) || (dX && !al16(dX)))))
+        return set_error(HH_ERR_UNSUPPORTED,
+                         "WY path needs n and leading dimensions multiples of 8 and 16-byte aligned data");
+    const BwdLayout L = bwd_layout(op, s, n, N);
+    if (h > 0 && !U) return set_error(HH_ERR_INVALID_ARG, "U must not be null");
+    if (N > 0 && (!X || !G)) return set_error(HH_ERR_INVALID_ARG, "X and dY must not be null");
+    if (sym && !lam) return set_error(HH_ERR_INVALID_ARG, "lam must not be null");
+    if (!ws) return set_error(HH_ERR_INVALID_ARG, "ws must not be null");
+    if (ws_bytes < L.total)
+        return set_error(HH_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", L.total, ws_bytes);
+    const bool want_params = dU || (sym && dlam);
+    if (!want_params && (!dX || N == 0)) return HH_OK;
+
+    char *base = static_cast<char *>(ws);
+    const bool bf = d->compute_dtype == HH_BF16;
+    hipError_t e = wy_setup_any(bf, s, static_cast<const float *>(U), ldu, n, h, base, L.base, true, st);
+    if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY setup launch: %s", hipGetErrorString(e));
+    if (sym) {
+        e = wy_fill_lam(static_cast<const float *>(lam), (int)n, s.npad,
+                        reinterpret_cast<float *>(base + L.base.lam), st);
+        if (e != hipSuccess) return set_error(HH_ERR_HIP, "launch: %s", hipGetErrorString(e));
+    }
+    const int64_t padn = (int64_t)L.m * (L.ldc - N);
+    if (padn > 0) {
+        const dim3 zg((unsigned)((padn + 255) / 256));
+        if (bf) {
+            hipLaunchKernelGGL((k_zero_cols<__bf16>), zg, dim3(256), 0, st, reinterpret_cast<__bf16 *>(base + L.cg), L.m, N, L.ldc);
+            hipLaunchKernelGGL((k_zero_cols<__bf16>), zg, dim3(256), 0, st, reinterpret_cast<__bf16 *>(base + L.cx), L.m, N, L.ldc);
+        } else {
+            hipLaunchKernelGGL((k_zero_cols<_Float16>), zg, dim3(256), 0, st, reinterpret_cast<_Float16 *>(base + L.cg), L.m, N, L.ldc);
+            hipLaunchKernelGGL((k_zero_cols<_Float16>), zg, dim3(256), 0, st, reinterpret_cast<_Float16 *>(base + L.cx), L.m, N, L.ldc);
+        }
+    }
+    WyArgs a{};
+    a.Yc = base + L.base.yc;
+    a.Yr = base + L.base.yr;
+    a.Tm = reinterpret_cast<const float *>(base + L.base.tm);
+    a.lam = reinterpret_cast<const float *>(base + L.base.lam);
+    a.ldc = L.ldc;
+    a.n = (int)n;
+    a.npad = s.npad;
+    a.N = N;
+    const WyOp xop = op == HH_OP_APPLY_BWD ? W_APPLY : op == HH_OP_APPLY_T_BWD ? W_APPLY_T : W_SYM;
+    const WyOp gop = op == HH_OP_APPLY_BWD ? W_APPLY_T : op == HH_OP_APPLY_T_BWD ? W_APPLY : W_SYM;
+    if (want_params) {  // pass over X: coefficients only
+        WyArgs ax = a;
+        ax.X = X;
+        ax.ldx = ldx;
+        ax.Y = const_cast<void *>(X);
+        ax.ldy = ldx;
+        ax.coef = base + L.cg;
+        ax.store = 0;
+        e = wy_main_any(bf, s, xop, ax, st);
+        if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY pass over X: %s", hipGetErrorString(e));
+    }
+    {  // pass over G: coefficients and dX
+        WyArgs ag = a;
+        ag.X = G;
+        ag.ldx = ldg;
+        ag.Y = dX ? dX : const_cast<void *>(G);
+        ag.ldy = dX ? lddx : ldg;
+        ag.coef = want_params ? base + L.cx : nullptr;
+        ag.store = dX ? 1 : 0;
+        e = wy_main_any(bf, s, gop, ag, st);
+        if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY pass over dY: %s", hipGetErrorString(e));
+    }
+    if (!want_params) return HH_OK;
+    e = bf ? launch_products<BF16>(s, L, base, G, ldg, X, ldx, N, (int)n, sym, st)
+           : launch_products<F16>(s, L, base, G, ldg, X, ldx, N, (int)n, sym, st);
+    if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY product launch: %s", hipGetErrorString(e));
+    const int hp = s.hp;
+    const int kind = op == HH_OP_APPLY_BWD ? 0 : op == HH_OP_APPLY_T_BWD ? 1 : 2;
+    const dim3 mg((hp * hp + 255) / 256);
+    hipLaunchKernelGGL(k_wy_mmat, mg, dim3(256), 0, st, reinterpret_cast<const float *>(base + L.gpart),
+                       L.ksg, hp, kind, reinterpret_cast<double *>(base + L.kd), nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_wy_mmat2, mg, dim3(256), 0, st, reinterpret_cast<const double *>(base + L.kd), hp,
+                       kind, reinterpret_cast<double *>(base + L.ma), reinterpret_cast<double *>(base + L.mb),
+                       reinterpret_cast<double *>(base + L.mc));
+    CombineArgs ca{};
+    ca.part = reinterpret_cast<const float *>(base + L.part);
+    ca.gx = sym ? reinterpret_cast<const float *>(base + L.gx) : nullptr;
+    ca.ks = L.ks;
+    ca.m = L.m;
+    ca.uh = reinterpret_cast<const double *>(base + L.base.uh64);
+    ca.Ma = reinterpret_cast<const double *>(base + L.ma);
+    ca.Mb = reinterpret_cast<const double *>(base + L.mb);
+    ca.Mc = reinterpret_cast<const double *>(base + L.mc);
+    ca.lam = reinterpret_cast<const float *>(base + L.base.lam);
+    ca.dV = reinterpret_cast<double *>(base + L.dv);
+    ca.dlam = sym ? static_cast<float *>(dlam) : nullptr;
+    ca.n = (int)n;
+    ca.h = (int)h;
+    ca.hp = hp;
+    ca.npad = s.npad;
+    ca.kind = kind;
+    hipLaunchKernelGGL(k_wy_combine, dim3(s.npad), dim3(hp), 0, st, ca);
+    if (dU && h > 0)
+        hipLaunchKernelGGL(k_wy_finish, dim3((unsigned)h), dim3(256), 0, st,
+                           reinterpret_cast<const double *>(base + L.dv), s.npad, (int)n,
+                           reinterpret_cast<const double *>(base + L.base.uh64),
+                           reinterpret_cast<const double *>(base + L.base.nrmraw), static_cast<float *>(dU),
+                           lddu);
+    e = hipGetLastError();
+    if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY finish launch: %s", hipGetErrorString(e));
+    return HH_OK;
+}
+
+}  // namespace hh

@@ -124,3 +124,95 @@ def test_wy_matches_fused_fp32():
     Yw = P.apply_raw(U, Xb, compute=torch.bfloat16).float()
     Yf = P.apply_raw(U, Xb.float())
     assert rel_rows(host(Yw), host(Yf)) < TOL16
+
+
+# ----------------------------------------------------------------------------
+# backward of the WY path
+# ----------------------------------------------------------------------------
+from tests._util import rel_fro  # noqa: E402
+
+BSHAPES = [(512, 9, 100), (1024, 64, 50), (4096, 64, 300), (2048, 100, 40), (8192, 128, 64),
+           (256, 3, 1000), (64, 1, 7)]
+
+
+@pytest.mark.parametrize("dname", ["bf16", "f16"])
+@pytest.mark.parametrize("n,h,N", BSHAPES)
+def test_wy_apply_bwd_parity(dname, n, h, N):
+    dt = DT[dname]
+    U, X = make(n, h, N, dt, seed=5 * n + h)
+    Uraw = U * torch.linspace(0.5, 2.0, h, device=dev())[:, None]  # non-unit columns
+    G = torch.tensor(synth.gaussian((N, n), seed=2, stream=synth.STREAM_G), dtype=torch.float32,
+                     device=dev()).to(dt)
+    for trans in (False, True):
+        dX, dU = P.apply_bwd_raw(Uraw, X, G, trans=trans, compute=dt)
+        torch.cuda.synchronize()
+        rdX, rdU = oracle.apply_bwd(host(Uraw), host(X), host(G), trans=trans)
+        assert rel_rows(host(dX), rdX) < TOL16, (trans, rel_rows(host(dX), rdX))
+        assert rel_fro(host(dU), rdU) < TOL16, (trans, rel_fro(host(dU), rdU))
+
+
+@pytest.mark.parametrize("dname", ["bf16", "f16"])
+@pytest.mark.parametrize("n,h,N", [(512, 9, 100), (1024, 64, 40), (2048, 100, 33), (8192, 128, 48)])
+def test_wy_sym_bwd_parity(dname, n, h, N):
+    dt = DT[dname]
+    U, X = make(n, h, N, dt, seed=7 * n + h)
+    lam = torch.tensor(synth.eig_loguniform(n, seed=2), dtype=torch.float32, device=dev())
+    G = torch.tensor(synth.gaussian((N, n), seed=3, stream=synth.STREAM_G), dtype=torch.float32,
+                     device=dev()).to(dt)
+    dX, dU, dlam = P.sym_bwd_raw(U, lam, X, G, compute=dt)
+    torch.cuda.synchronize()
+    rdX, rdU, rdlam = oracle.sym_bwd(host(U), host(lam), host(X), host(G))
+    assert rel_rows(host(dX), rdX) < TOL16, rel_rows(host(dX), rdX)
+    assert rel_fro(host(dU), rdU) < TOL16, rel_fro(host(dU), rdU)
+    assert rel_fro(host(dlam), rdlam) < TOL16, rel_fro(host(dlam), rdlam)
+
+
+def test_wy_bwd_edge_cases():
+    dt = torch.bfloat16
+    n = 256
+    U, X = make(n, 6, 0, dt)
+    E = torch.empty((0, n), dtype=dt, device=dev())
+    lam = torch.ones(n, device=dev())
+    dX, dU, dlam = P.sym_bwd_raw(U, lam, E, E, compute=dt)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(dU) == 0 and torch.count_nonzero(dlam) == 0
+    # h = 0: dX = S G = lam * G; dlam = sum_j G X
+    U0 = torch.zeros((0, n), device=dev())
+    _, X = make(n, 1, 40, dt)
+    G = torch.randn((40, n), device=dev()).to(dt)
+    lam = torch.rand(n, device=dev()) + 0.5
+    dX, dU, dlam = P.sym_bwd_raw(U0, lam, X, G, compute=dt)
+    rdX, _, rdlam = oracle.sym_bwd(np.zeros((0, n)), host(lam), host(X), host(G))
+    assert rel_rows(host(dX), rdX) < TOL16
+    assert rel_fro(host(dlam), rdlam) < 1e-3
+    # zero reflector column: zero gradient column
+    U, X = make(n, 5, 33, dt)
+    U[1] = 0
+    G = torch.randn((33, n), device=dev()).to(dt)
+    _, dU = P.apply_bwd_raw(U, X, G, compute=dt)
+    assert torch.count_nonzero(dU[1]) == 0
+    _, rdU = oracle.apply_bwd(host(U), host(X), host(G))
+    assert rel_fro(host(dU), rdU) < TOL16
+
+
+def test_wy_bwd_deterministic():
+    dt = torch.float16
+    U, X = make(1024, 64, 500, dt)
+    G = torch.randn_like(X)
+    a = P.apply_bwd_raw(U, X, G, compute=dt)[1]
+    b = P.apply_bwd_raw(U, X, G, compute=dt)[1]
+    assert torch.equal(a, b)
+
+
+def test_wy_autograd():
+    dt = torch.bfloat16
+    n, h, N = 512, 16, 64
+    U, X = make(n, h, N, dt)
+    U.requires_grad_(True)
+    lam = torch.tensor(synth.eig_uniform(n), dtype=torch.float32, device=dev(), requires_grad=True)
+    G = torch.randn((N, n), device=dev()).to(dt)
+    Y = P.sym_apply(U, lam, X, compute=dt)
+    (Y.float() * G.float()).sum().backward()
+    _, rdU, rdlam = oracle.sym_bwd(host(U), host(lam), host(X), host(G))
+    assert rel_fro(host(U.grad), rdU) < TOL16
+    assert rel_fro(host(lam.grad), rdlam) < TOL16
