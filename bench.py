@@ -46,6 +46,11 @@ WORKLOADS = {
                          "Mahalanobis forward + backward to U and lam, n=512, h=9, N=2^22; fused FP32"),
     "qx_n64_h4_f64": ("apply", 64, 4, 1024, "f64",
                       "Q X, n=64, h=4, N=1024; fused FP64"),
+    "qx_fb_n4096_h64": ("apply_fb", 4096, 64, 1 << 18, "bf16",
+                        "Q X forward + backward (dX, dU), n=4096, h=64, N=2^18; compact-WY BF16"),
+    "sym_fb_n8192_h128": ("sym_fb", 8192, 128, 1 << 16, "f16",
+                          "Q diag(lam) Q^T X forward + backward (dX, dU, dlam), n=8192, h=128, "
+                          "N=2^16; compact-WY FP16"),
     "copy_n4096_bf16": ("copy", 4096, 0, 1 << 18, "bf16",
                         "device copy of the Q X batch (2 GiB in, 2 GiB out): HBM calibration"),
 }
@@ -75,6 +80,10 @@ def algorithmic(op, n, h, N, io_bytes, param_bytes=4):
         return 2 * n * io_bytes * N, (8 * h + 1) * n * N
     if op == "mahal":
         return (2 * n * io_bytes + param_bytes) * N, (4 * h + 3) * n * N
+    if op == "apply_fb":   # forward: X in, Y out; backward: X, dY in, dX out
+        return 5 * n * io_bytes * N, (4 * n * h + 2 * h * h) * 4 * N
+    if op == "sym_fb":     # ~24 n h per vector for forward + backward on the matrix cores
+        return 5 * n * io_bytes * N, 24 * n * h * N
     if op == "mahal_fb":
         fwd = (2 * n * io_bytes + param_bytes) * N
         bwd = (2 * n * io_bytes + param_bytes) * N
@@ -127,7 +136,8 @@ def main():
     pdt = torch.float64 if comp == "f64" else torch.float32
 
     U = torch.tensor(synth.reflectors(n, h, seed=0), dtype=pdt, device=dev)
-    lam = torch.tensor(synth.eig_uniform(n, seed=0), dtype=pdt, device=dev)
+    lam_np = (synth.eig_loguniform(n, seed=0) if op == "sym_fb" else synth.eig_uniform(n, seed=0))
+    lam = torch.tensor(lam_np, dtype=pdt, device=dev)
     X = synth.device_gaussian((N, n), seed=0, stream=synth.STREAM_X, device=dev, dtype=io_dt)
     Xb = None
     w = None
@@ -135,7 +145,10 @@ def main():
         Xb = synth.device_gaussian((N, n), seed=0, stream=synth.STREAM_XB, device=dev, dtype=io_dt)
     if op == "mahal_fb":
         w = synth.device_gaussian((N,), seed=0, stream=synth.STREAM_W, device=dev, dtype=pdt)
-    Y = torch.empty_like(X) if op in ("apply", "sym", "copy") else None
+    Gd = None
+    if op in ("apply_fb", "sym_fb"):
+        Gd = synth.device_gaussian((N, n), seed=0, stream=synth.STREAM_G, device=dev, dtype=io_dt)
+    Y = torch.empty_like(X) if op in ("apply", "sym", "copy", "apply_fb", "sym_fb") else None
     torch.cuda.synchronize()
 
     def step():
@@ -147,6 +160,12 @@ def main():
             P.sym_raw(U, lam, X, compute=tdt, out=Y)
         elif op == "mahal":
             P.mahal_raw(U, lam, X, Xb)
+        elif op == "apply_fb":
+            P.apply_raw(U, X, compute=tdt, out=Y)
+            P.apply_bwd_raw(U, X, Gd, compute=tdt)
+        elif op == "sym_fb":
+            P.sym_raw(U, lam, X, compute=tdt, out=Y)
+            P.sym_bwd_raw(U, lam, X, Gd, compute=tdt)
         else:
             P.mahal_raw(U, lam, X, Xb)
             P.mahal_bwd_raw(U, lam, X, Xb, w, need_dX=False)
@@ -174,6 +193,9 @@ def main():
     abytes, aflops = algorithmic(op, n, h, N, io_bytes, 8 if comp == "f64" else 4)
     if comp in ("bf16", "f16"):
         bound, peak, unit, ach = "hbm", HBM_PEAK_GBS, "GB/s", abytes / (ms_ev * 1e-3) / 1e9
+        if op == "sym_fb" and aflops / (MFMA_BF16_TFLOPS * 1e12) > abytes / (HBM_PEAK_GBS * 1e9):
+            bound, peak, unit = "mfma", MFMA_BF16_TFLOPS, "TFLOP/s"
+            ach = aflops / (ms_ev * 1e-3) / 1e12
     else:
         t_hbm = abytes / (HBM_PEAK_GBS * 1e9)
         t_alu = aflops / ((FP64_VALU_TFLOPS if comp == "f64" else FP32_VALU_TFLOPS) * 1e12)
@@ -231,7 +253,43 @@ def main():
         Y = None
 
     # accuracy on a sample of vectors, and the oracle's own speed on it
-    if not args.no_cpu and op != "copy":
+    if not args.no_cpu and op in ("apply_fb", "sym_fb"):
+        import oracle
+        Uh = U.double().cpu().numpy()
+        lh = lam.double().cpu().numpy()
+        S = min(N, 256)
+        Xs, Gs = X[:S], Gd[:S]
+        if op == "apply_fb":
+            dXg, dUg = P.apply_bwd_raw(U, Xs, Gs, compute=tdt)
+            Yg = P.apply_raw(U, Xs, compute=tdt)
+        else:
+            dXg, dUg, dlg = P.sym_bwd_raw(U, lam, Xs, Gs, compute=tdt)
+            Yg = P.sym_raw(U, lam, Xs, compute=tdt)
+        torch.cuda.synchronize()
+        xh, gh = Xs.double().cpu().numpy(), Gs.double().cpu().numpy()
+        t = time.perf_counter()
+        if op == "apply_fb":
+            ry = oracle.apply(Uh, xh)
+            rdx, rdu = oracle.apply_bwd(Uh, xh, gh)
+        else:
+            ry = oracle.sym(Uh, lh, xh)
+            rdx, rdu, rdl = oracle.sym_bwd(Uh, lh, xh, gh)
+        tcpu = time.perf_counter() - t
+
+        def rr(a, b):
+            a = a.double().cpu().numpy()
+            return float(np.max(np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)))
+
+        def rf(a, b):
+            a = a.double().cpu().numpy()
+            return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        out["max_rel_err_sample"] = {"Y": rr(Yg, ry), "dX": rr(dXg, rdx), "dU": rf(dUg, rdu)}
+        if op == "sym_fb":
+            out["max_rel_err_sample"]["dlam"] = rf(dlg, rdl)
+        out["cpu_baseline"] = {"value": S / tcpu, "unit": "vectors/s (forward + backward)",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"first {S} of {N} vectors of the same batch, FP64"}
+    if not args.no_cpu and op in ("apply", "sym", "mahal", "mahal_fb"):
         import oracle
         Uh = U.double().cpu().numpy()
         lh = lam.double().cpu().numpy()
