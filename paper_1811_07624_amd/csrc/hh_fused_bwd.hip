@@ -29,15 +29,6 @@
 namespace hh {
 namespace {
 
-template <typename F, int... I>
-__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
-    (f(std::integral_constant<int, I>{}), ...);
-}
-// Calls f(integral_constant<int, i>) for i = 0 .. N-1 (compile-time indices).
-template <int N, typename F> __device__ __forceinline__ void static_for(F &&f) {
-    static_for_impl(f, std::make_integer_sequence<int, N>{});
-}
-
 constexpr int kWPB = 4;
 constexpr int kThreads = kWPB * kWave;
 constexpr size_t kLdsBudget = 64 * 1024;

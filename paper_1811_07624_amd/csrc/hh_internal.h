@@ -8,12 +8,22 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <utility>
 
 #include "hh.h"
 
 namespace hh {
 
 constexpr int kWave = 64;
+
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+// Calls f(integral_constant<int, i>) for i = 0 .. N-1 (compile-time indices).
+template <int N, typename F> __device__ __forceinline__ void static_for(F &&f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 // ---------------------------------------------------------------------------
 // 16-byte vector types: the unit of every global and LDS access of the fused

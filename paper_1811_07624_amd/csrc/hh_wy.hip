@@ -52,6 +52,7 @@ __global__ __launch_bounds__(256) void k_wy_norm(const float *__restrict__ U, in
                                                 int h, int npad, int hp,
                                                 typename E::elem *__restrict__ Yc,
                                                 typename E::elem *__restrict__ Yr,
+                                                typename E::elem *__restrict__ Ycs,
                                                 double *__restrict__ nrm2,
                                                 double *__restrict__ nrm_raw,
                                                 double *__restrict__ uh64) {
@@ -80,6 +81,7 @@ __global__ __launch_bounds__(256) void k_wy_norm(const float *__restrict__ U, in
         const el y = (el)v;
         Yc[yc_index(k, i, npad)] = y;
         Yr[yr_index(k, i, hp)] = y;
+        Ycs[ycs_index(k, i, hp)] = y;
         if (uh64 && k < h && i < n) uh64[(int64_t)k * n + i] = v;
         const double yd = (double)y;
         s2 += yd * yd;
@@ -96,74 +98,149 @@ __global__ __launch_bounds__(256) void k_wy_norm(const float *__restrict__ U, in
     }
 }
 
-// G[a][b] = y_a . y_b for a < b, FP64 (products of 16-bit values are exact).
+// Partial Gram matrices of the rounded reflectors in FP64 (a product of two
+// 16-bit values is exact): Gp[s][a][b] = sum over the rows of segment s of
+// y_a y_b, for the 16 x 16 tiles (ta, tb), ta <= tb, one block per (tile
+// pair, segment).  Each step stages the fragments (ta, q) and (tb, q) of the
+// fragment-ordered copy (32 rows each) in LDS.
 template <typename E>
-__global__ __launch_bounds__(256) void k_wy_gram(const typename E::elem *__restrict__ Yc,
-                                                int npad, int hp, double *__restrict__ G) {
-    __shared__ double red[256];
-    const int a = blockIdx.y, b = blockIdx.x;
-    const int t = threadIdx.x;
-    if (b <= a) {
-        if (t == 0) G[a * hp + b] = 0.0;
-        return;
+__global__ __launch_bounds__(256) void k_wy_gram(const typename E::elem *__restrict__ Yc, int npad,
+                                                int hp, double *__restrict__ Gp) {
+    using v8 = typename E::vec8;
+    __shared__ double ya[32][17], yb[32][17];
+    const int nhb = hp >> 4;
+    int pr = blockIdx.x, ta = 0;
+    while (pr >= nhb - ta) {
+        pr -= nhb - ta;
+        ++ta;
     }
-    double s = 0.0;
-    for (int i = t; i < npad; i += 256)
-        s += (double)Yc[yc_index(a, i, npad)] * (double)Yc[yc_index(b, i, npad)];
-    red[t] = s;
-    __syncthreads();
-    for (int q = 128; q > 0; q >>= 1) {
-        if (t < q) red[t] += red[t + q];
+    const int tb = ta + pr;
+    const int nq = npad >> 5, qs = nq / kGramSeg, seg = blockIdx.y;
+    const int t = threadIdx.x, i = t >> 4, j = t & 15;
+    double acc = 0.0;
+    for (int q = seg * qs; q < (seg + 1) * qs; ++q) {
         __syncthreads();
+        if (t < 128) {
+            const int which = t >> 6, ln = t & 63;
+            const int hb = which ? tb : ta;
+            const v8 v = *reinterpret_cast<const v8 *>(Yc + ((size_t)(hb * nq + q) * 64 + ln) * 8);
+            double(*dst)[17] = which ? yb : ya;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dst[8 * (ln >> 4) + e][ln & 15] = (double)v[e];
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int r = 0; r < 32; ++r) acc += ya[r][i] * yb[r][j];
     }
-    if (t == 0) G[a * hp + b] = red[0];
+    Gp[((size_t)seg * hp + 16 * ta + i) * hp + 16 * tb + j] = acc;
 }
 
-// T = (diag(||y_k||^2/2) + striu(G))^{-1}, upper triangular, in FP64.  Rows
-// are solved bottom-up, all columns of a row in parallel:
-//   T[i][j] = (delta_ij - sum_{k=i+1..j} G[i][k] T[k][j]) / d_i,  j >= i.
-// One LDS array holds both matrices: G transposed below the diagonal
-// (M[k][i] = G[i][k], k > i) and T on and above it.  Tm = T as FP32,
-// row-major; Tw = T in FP64 (zero below the diagonal).
+// T = (diag(||y_k||^2/2) + striu(G))^{-1}, upper triangular, FP64, by blocked
+// inversion in LDS: the 16 x 16 diagonal blocks are inverted by back
+// substitution (one column per thread), then neighbouring inverted blocks of
+// [A B; 0 C] are merged, the off-diagonal block becoming -A^{-1} (B C^{-1}),
+// doubling the block size at each level (each thread forms a 4 x 4 piece).
+// Tm = T as FP32, row-major; Tw = T in FP64 (zero below the diagonal).
 __global__ __launch_bounds__(256) void k_wy_tmat(const double *__restrict__ G,
                                                 const double *__restrict__ nrm2, int hp,
                                                 double *__restrict__ Tw, float *__restrict__ Tm) {
     extern __shared__ double M[];
+    const int LD = hp + 1;
     const int t = threadIdx.x;
-    // hp * hp is a multiple of 256*16 for hp in {64, 128}: unrolled, all loads in flight
-    const int per = hp * hp / 256;
-#pragma unroll 16
-    for (int r = 0; r < per; ++r) {
-        const int idx = r * 256 + t;
+#pragma unroll 8
+    for (int idx = t; idx < hp * hp; idx += 256) {
         const int i = idx / hp, k = idx % hp;
-        const double v = G[idx];
-        if (i < k) M[k * hp + i] = v;
+        const double g = G[idx];
+        M[i * LD + k] = k > i ? g : k < i ? 0.0 : (nrm2[i] > 0.0 ? 0.5 * nrm2[i] : 0.5);
     }
     __syncthreads();
-    const int j = t;
-    for (int i = hp - 1; i >= 0; --i) {
-        if (j >= i && j < hp) {
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            int k = i + 1;
-            for (; k + 3 <= j; k += 4) {
-                a0 += M[k * hp + i] * M[k * hp + j];
-                a1 += M[(k + 1) * hp + i] * M[(k + 1) * hp + j];
-                a2 += M[(k + 2) * hp + i] * M[(k + 2) * hp + j];
-                a3 += M[(k + 3) * hp + i] * M[(k + 3) * hp + j];
+    {
+        const bool act = t < hp;  // hp / 16 blocks x 16 columns
+        const int o = 16 * (t >> 4), jc = t & 15;
+        double x[16];
+        if (act) {
+#pragma unroll
+            for (int i = 15; i >= 0; --i) {
+                double s = (i == jc) ? 1.0 : 0.0;
+#pragma unroll
+                for (int k = i + 1; k < 16; ++k) s -= M[(o + i) * LD + o + k] * x[k];
+                x[i] = (i > jc) ? 0.0 : s / M[(o + i) * LD + o + i];
             }
-            for (; k <= j; ++k) a0 += M[k * hp + i] * M[k * hp + j];
-            const double d = nrm2[i] > 0.0 ? 0.5 * nrm2[i] : 0.5;
-            M[i * hp + j] = ((i == j ? 1.0 : 0.0) - ((a0 + a1) + (a2 + a3))) / d;
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) M[(o + i) * LD + o + jc] = x[i];
         }
         __syncthreads();
     }
-#pragma unroll 16
-    for (int r = 0; r < per; ++r) {
-        const int idx = r * 256 + t;
+    for (int s = 16; s < hp; s *= 2) {
+        const int tq = s / 4;
+        const bool act = t < (hp / (2 * s)) * tq * tq;
+        const int pidx = t / (tq * tq), rr = t % (tq * tq);
+        const int i0 = 2 * s * pidx, a0 = i0 + 4 * (rr / tq), b0 = i0 + s + 4 * (rr % tq);
+        double acc[4][4];
+        for (int step = 0; step < 2; ++step) {
+            if (act) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[q][r] = 0.0;
+                // step 0: B C^{-1} (C^{-1} at rows/cols i0+s..); step 1: A^{-1} X (X in B's place)
+                const int ka = step == 0 ? i0 + s : i0;
+                for (int c = 0; c < s; ++c) {
+                    double av[4], bv[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        av[q] = M[(a0 + q) * LD + ka + c];
+                        bv[q] = M[(ka + c) * LD + b0 + q];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[q][r] += av[q] * bv[r];
+                }
+            }
+            __syncthreads();
+            if (act) {
+                const double sg = step == 0 ? 1.0 : -1.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) M[(a0 + q) * LD + b0 + r] = sg * acc[q][r];
+            }
+            __syncthreads();
+        }
+    }
+    for (int idx = t; idx < hp * hp; idx += 256) {
         const int i = idx / hp, k = idx % hp;
-        const double v = (k >= i) ? M[idx] : 0.0;
+        const double v = (k >= i) ? M[i * LD + k] : 0.0;
         Tw[idx] = v;
         Tm[idx] = (float)v;
+    }
+}
+
+// T (tr = 0) and T^T (tr = 1) as 16-bit MFMA A-operand fragments split into
+// hi + lo parts (hi = T rounded, lo = the rest rounded), for the streaming
+// kernel's T product.  Fragment (tr, hl, ib, kb), lane (c, g), element j holds
+// T'[sigma_row(ib, c)][32 kb + 8 g + j].  One thread per (fragment, lane).
+template <typename E>
+__global__ __launch_bounds__(256) void k_wy_tfrag(const double *__restrict__ Tw, int hp,
+                                                 typename E::elem *__restrict__ Tf) {
+    using el = typename E::elem;
+    const int HB = hp >> 4, KS = hp >> 5;
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= 4 * HB * KS * 64) return;
+    const int lane = id & 63, f = id >> 6;
+    const int kb = f % KS, ib = (f / KS) % HB, hl = (f / (KS * HB)) & 1, tr = f / (2 * KS * HB);
+    const int c = lane & 15, g = lane >> 4;
+    const int r = sigma_row(ib, c);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int col = 32 * kb + 8 * g + j;
+        const double t = tr ? Tw[col * hp + r] : Tw[r * hp + col];
+        const el hi = (el)t;
+        Tf[(size_t)id * 8 + j] = hl ? (el)(t - (double)hi) : hi;
     }
 }
 
@@ -455,16 +532,24 @@ hipError_t wy_setup(const WyShape &s, const float *U, int64_t ldu, int64_t n, in
     const int hp = s.hp;
     hipLaunchKernelGGL((k_wy_norm<E>), dim3(hp), dim3(256), 0, st, U, ldu, (int)n, (int)h, s.npad,
                        hp, reinterpret_cast<el *>(ws + w.yc), reinterpret_cast<el *>(ws + w.yr),
+                       reinterpret_cast<el *>(ws + w.ycs),
                        reinterpret_cast<double *>(ws + w.nrm2),
                        reinterpret_cast<double *>(ws + w.nrmraw),
                        want_uh ? reinterpret_cast<double *>(ws + w.uh64) : nullptr);
-    hipLaunchKernelGGL((k_wy_gram<E>), dim3(hp, hp), dim3(256), 0, st,
+    const int nhb = hp / 16;
+    hipLaunchKernelGGL((k_wy_gram<E>), dim3(nhb * (nhb + 1) / 2, kGramSeg), dim3(256), 0, st,
                        reinterpret_cast<const el *>(ws + w.yc), s.npad, hp,
                        reinterpret_cast<double *>(ws + w.gram));
-    hipLaunchKernelGGL(k_wy_tmat, dim3(1), dim3(256), (size_t)hp * hp * 8, st,
-                       reinterpret_cast<const double *>(ws + w.gram),
+    hipLaunchKernelGGL((k_sum_parts<double>), dim3(hp * hp / 32, 1), dim3(256), 0, st,
+                       reinterpret_cast<const double *>(ws + w.gram), kGramSeg, (size_t)hp * hp, hp * hp,
+                       reinterpret_cast<double *>(ws + w.gsum));
+    hipLaunchKernelGGL(k_wy_tmat, dim3(1), dim3(256), (size_t)hp * (hp + 1) * 8, st,
+                       reinterpret_cast<const double *>(ws + w.gsum),
                        reinterpret_cast<const double *>(ws + w.nrm2), hp,
                        reinterpret_cast<double *>(ws + w.tw), reinterpret_cast<float *>(ws + w.tm));
+    const int nfrag = 4 * (hp / 16) * (hp / 32) * 64;
+    hipLaunchKernelGGL((k_wy_tfrag<E>), dim3((nfrag + 255) / 256), dim3(256), 0, st,
+                       reinterpret_cast<const double *>(ws + w.tw), hp, reinterpret_cast<el *>(ws + w.tf));
     return hipGetLastError();
 }
 
@@ -514,8 +599,32 @@ hipError_t wy_fill_lam(const float *lam, int n, int npad, float *out, hipStream_
     return hipGetLastError();
 }
 
+// Which main kernel runs: 0 = register-resident tile, 1 = streaming, 2 = by shape.
+#ifndef HH_WY_STREAM_POLICY
+#define HH_WY_STREAM_POLICY 2
+#endif
+
+// The register-resident kernel reads X once and writes it once but streams
+// the whole reflector matrix from L2 for every 16-32 vectors; the streaming
+// kernel amortises that stream over 128 vectors at the price of one extra
+// read of X per phase.  Measured on MI355X (bf16 / fp16): at n hp = 2^18
+// (n = 4096, h = 64) Q X takes 1.40 ms resident vs 1.56 ms streaming for
+// 2^18 vectors; at n hp = 2^20 (n = 8192, h = 128) Q diag(lam) Q^T X takes
+// 1.66 ms vs 1.35 ms for 2^16 vectors.  A pass that only emits the
+// backward's coefficients reads X once in either kernel, and streams faster.
+static bool use_stream(const WyShape &s, const WyArgs &a) {
+    // 32-bit buffer offsets: a tile of 256 vectors and the coefficient rows
+    const int64_t lim = (int64_t)1 << 31;
+    if (256 * std::max(a.ldx, a.ldy) * 2 >= lim) return false;
+    if (a.coef && 4 * (int64_t)s.hp * a.ldc >= lim) return false;
+    if (HH_WY_STREAM_POLICY == 0) return false;
+    if (HH_WY_STREAM_POLICY == 1) return true;
+    return (int64_t)a.n * s.hp >= (int64_t)1 << 19 || !a.store;
+}
+
 hipError_t wy_main_any(bool bf, const WyShape &s, WyOp op, const WyArgs &a, hipStream_t st) {
     if (a.N == 0) return hipSuccess;
+    if (use_stream(s, a)) return wy_stream_any(bf, s, op, a, st);
     return bf ? dispatch_main<BF16>(s, op, a, st) : dispatch_main<F16>(s, op, a, st);
 }
 
@@ -575,6 +684,8 @@ hh_status wy_forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, con
     a.ldy = ldy;
     a.Yc = base + w.yc;
     a.Yr = base + w.yr;
+    a.Ycs = base + w.ycs;
+    a.Tf = base + w.tf;
     a.Tm = reinterpret_cast<const float *>(base + w.tm);
     a.lam = reinterpret_cast<const float *>(base + w.lam);
     a.store = 1;
@@ -582,7 +693,7 @@ hh_status wy_forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, con
     a.npad = s.npad;
     a.N = N;
     const WyOp wop = op == HH_OP_APPLY ? W_APPLY : op == HH_OP_APPLY_T ? W_APPLY_T : W_SYM;
-    e = bf ? dispatch_main<BF16>(s, wop, a, st) : dispatch_main<F16>(s, wop, a, st);
+    e = wy_main_any(bf, s, wop, a, st);
     if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY kernel launch: %s", hipGetErrorString(e));
     return HH_OK;
 }

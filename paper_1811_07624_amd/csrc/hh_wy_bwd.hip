@@ -212,30 +212,16 @@ __global__ void k_zero_cols(T *p, int m, int64_t N, int64_t ldc) {
     if (i < (int64_t)m * pad) p[(i / pad) * ldc + N + i % pad] = (T)0;
 }
 
-// K[pair][e] = sum over splits (FP64, fixed order); then the h x h matrices the
-// combine step needs, stored transposed (Mt[k][l] = M[l][k]):
+// From the coefficient Grams K[pair] (summed over vector splits in FP64), the
+// h x h matrices the combine step needs, stored as M[l][k] at l * hp + k:
 //   Ma = K1 + K1^T (symmetric form only), Mb = the order-dependent triangles,
 //   Mc = K1 (symmetric form only).
-__global__ __launch_bounds__(256) void k_wy_mmat(const float *__restrict__ part, int ksg, int hp,
-                                                int kind, double *__restrict__ Kd,
-                                                double *__restrict__ Ma, double *__restrict__ Mb,
-                                                double *__restrict__ Mc) {
-    const int npairs = kind == 2 ? 3 : 1;
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= hp * hp) return;
-    for (int pr = 0; pr < npairs; ++pr) {
-        double s = 0.0;
-        for (int q = 0; q < ksg; ++q) s += (double)part[((size_t)pr * ksg + q) * hp * hp + e];
-        Kd[(size_t)pr * hp * hp + e] = s;
-    }
-}
-
 __global__ __launch_bounds__(256) void k_wy_mmat2(const double *__restrict__ Kd, int hp, int kind,
                                                  double *__restrict__ Ma, double *__restrict__ Mb,
                                                  double *__restrict__ Mc) {
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= hp * hp) return;
-    const int k = e / hp, l = e % hp;  // Mt[k][l] = M[l][k]
+    const int l = e / hp, k = e % hp;  // stored M[l][k] at l * hp + k
     auto K = [&](int pr, int i, int j) { return Kd[(size_t)pr * hp * hp + i * hp + j]; };
     double mb = 0.0;
     if (kind == 0) {         // Q X: chain visits k = h..1 -> striu(K) + stril(K^T)
@@ -252,62 +238,94 @@ __global__ __launch_bounds__(256) void k_wy_mmat2(const double *__restrict__ Kd,
 }
 
 struct CombineArgs {
-    const float *part;   // [KS][npad][m]
-    const float *gx;     // nullable [KS][2][npad]
-    int ks, m;
+    const double *part;  // [npad][m], rank-N product summed over the vector splits
+    const double *gx;    // nullable [npad], sum_j G_rj X_rj
+    int m;
     const double *uh;    // h x n, FP64 unit reflectors
-    const double *Ma, *Mb, *Mc;  // transposed hp x hp
+    const double *Ma, *Mb, *Mc;  // hp x hp, M[l][k] at l * hp + k
     const float *lam;    // padded spectrum (symmetric form)
     double *dV;          // hp x npad
     float *dlam;         // nullable, n
-    int n, h, hp, npad, kind;
+    int n, h, npad, kind;
 };
 
-// One block per row r, one thread per reflector k (blockDim = hp).
-__global__ __launch_bounds__(128) void k_wy_combine(CombineArgs a) {
-    __shared__ double yr[128];
-    __shared__ double red[128];
-    const int r = blockIdx.x;
-    const int k = threadIdx.x;
-    const int hp = a.hp;
-    yr[k] = (k < a.h && r < a.n) ? a.uh[(size_t)k * a.n + r] : 0.0;
-    __syncthreads();
-    double o1 = 0.0, o2 = 0.0;
-    for (int s = 0; s < a.ks; ++s) {
-        const float *row = a.part + ((size_t)s * a.npad + r) * a.m;
-        o1 += (double)row[k];
-        if (a.kind == 2) o2 += (double)row[hp + k];
+// dV[k][r] = -(rank-N product)[r][k] + sum_l y[r][l] M[l][k] (plus the lam
+// terms of the symmetric form).  256 threads: thread k = t % HP owns reflector
+// k for RT consecutive rows of its row group t / HP.  The y rows of the block
+// sit in LDS; the M matrices pass through LDS LC rows at a time, each element
+// serving RT rows.
+template <int HP>
+__global__ __launch_bounds__(256) void k_wy_combine(CombineArgs a) {
+    constexpr int NG = 256 / HP, RT = 32 / NG, R = 32, LC = 8;
+    __shared__ double ys[R][HP + 1];
+    __shared__ double sm[3][LC][HP];
+    const int t = threadIdx.x;
+    const int k = t % HP, grp = t / HP;
+    const int r0 = blockIdx.x * R;
+    const bool sym = a.kind == 2;
+    const int nm = sym ? 3 : 1;
+    for (int e = t; e < R * HP; e += 256) {
+        const int kk = e / R, rr = e % R, r = r0 + rr;
+        ys[rr][kk] = (kk < a.h && r < a.n) ? a.uh[(size_t)kk * a.n + r] : 0.0;
     }
-    double yb = 0.0, ya = 0.0, yc = 0.0;
-    for (int l = 0; l < hp; ++l) {
-        const double y = yr[l];
-        yb += y * a.Mb[(size_t)k * hp + l];
-        if (a.kind == 2) {
-            ya += y * a.Ma[(size_t)k * hp + l];
-            yc += y * a.Mc[(size_t)k * hp + l];
-        }
-    }
-    double dv, contrib = 0.0;
-    if (a.kind == 2) {
-        const double lr = (r < a.n) ? (double)a.lam[r] : 0.0;
-        dv = -lr * o1 - o2 + lr * ya + yb;
-        contrib = -yr[k] * o1 + yc * yr[k];
-    } else {
-        dv = -o1 + yb;
-    }
-    a.dV[(size_t)k * a.npad + r] = dv;
-    if (a.kind == 2 && a.dlam) {
-        red[k] = contrib;
+    double yb[RT], ya[RT], yc[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) yb[i] = ya[i] = yc[i] = 0.0;
+    for (int l0 = 0; l0 < HP; l0 += LC) {
         __syncthreads();
-        for (int q = hp / 2; q > 0; q >>= 1) {
-            if (k < q) red[k] += red[k + q];
-            __syncthreads();
+        for (int mi = 0; mi < nm; ++mi) {
+            const double *src = (mi == 0 ? a.Mb : mi == 1 ? a.Ma : a.Mc) + (size_t)l0 * HP;
+#pragma unroll
+            for (int q = 0; q < LC * HP / 256; ++q) {
+                const int e = q * 256 + t;
+                sm[mi][e / HP][e % HP] = src[e];
+            }
         }
-        if (k == 0 && r < a.n) {
-            double gx = 0.0;
-            if (a.gx)
-                for (int s = 0; s < 2 * a.ks; ++s) gx += (double)a.gx[(size_t)s * a.npad + r];
-            a.dlam[r] = (float)(gx + red[0]);
+        __syncthreads();
+#pragma unroll
+        for (int ll = 0; ll < LC; ++ll) {
+            const double mb = sm[0][ll][k];
+            const double ma = sym ? sm[1][ll][k] : 0.0;
+            const double mc = sym ? sm[2][ll][k] : 0.0;
+#pragma unroll
+            for (int i = 0; i < RT; ++i) {
+                const double y = ys[grp * RT + i][l0 + ll];
+                yb[i] += y * mb;
+                ya[i] += y * ma;
+                yc[i] += y * mc;
+            }
+        }
+    }
+    double contrib[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        const int r = r0 + grp * RT + i;
+        const double *row = a.part + (size_t)r * a.m;
+        const double o1 = row[k];
+        const double o2 = sym ? row[HP + k] : 0.0;
+        double dv;
+        if (sym) {
+            const double lr = (double)a.lam[r];  // padded with zeros past n
+            const double yk = ys[grp * RT + i][k];
+            dv = -lr * o1 - o2 + lr * ya[i] + yb[i];
+            contrib[i] = -yk * o1 + yc[i] * yk;
+        } else {
+            dv = -o1 + yb[i];
+            contrib[i] = 0.0;
+        }
+        a.dV[(size_t)k * a.npad + r] = dv;
+    }
+    if (!sym || !a.dlam) return;
+    __syncthreads();  // reuse ys for the per-row sums over k
+#pragma unroll
+    for (int i = 0; i < RT; ++i) ys[grp * RT + i][k] = contrib[i];
+    __syncthreads();
+    if (t < R) {
+        const int r = r0 + t;
+        if (r < a.n) {
+            double s = 0.0;
+            for (int kk = 0; kk < HP; ++kk) s += ys[t][kk];
+            a.dlam[r] = (float)((a.gx ? a.gx[r] : 0.0) + s);
         }
     }
 }
@@ -342,7 +360,7 @@ struct BwdLayout {
     int64_t ldc;
     int m, ks, ksg, npairs;
     int64_t chunk, gchunk;
-    size_t cg, cx, part, gx, gpart, kd, ma, mb, mc, dv, total;
+    size_t cg, cx, part, gx, psum, gxsum, gpart, kd, ma, mb, mc, dv, total;
 };
 
 BwdLayout bwd_layout(hh_op op, const WyShape &s, int64_t n, int64_t N) {
@@ -366,6 +384,8 @@ BwdLayout bwd_layout(hh_op op, const WyShape &s, int64_t n, int64_t N) {
     L.cx = off;    off += align256((size_t)L.m * L.ldc * 2);
     L.part = off;  off += align256((size_t)L.ks * s.npad * L.m * 4);
     L.gx = off;    off += sym ? align256((size_t)L.ks * 2 * s.npad * 4) : 0;
+    L.psum = off;  off += align256((size_t)s.npad * L.m * 8);
+    L.gxsum = off; off += sym ? align256((size_t)s.npad * 8) : 0;
     L.gpart = off; off += align256((size_t)L.npairs * L.ksg * hp * hp * 4);
     L.kd = off;    off += align256((size_t)L.npairs * hp * hp * 8);
     L.ma = off;    off += align256(hp * hp * 8);
@@ -483,6 +503,8 @@ hh_status wy_backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, co
     WyArgs a{};
     a.Yc = base + L.base.yc;
     a.Yr = base + L.base.yr;
+    a.Ycs = base + L.base.ycs;
+    a.Tf = base + L.base.tf;
     a.Tm = reinterpret_cast<const float *>(base + L.base.tm);
     a.lam = reinterpret_cast<const float *>(base + L.base.lam);
     a.ldc = L.ldc;
@@ -520,15 +542,25 @@ hh_status wy_backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, co
     const int hp = s.hp;
     const int kind = op == HH_OP_APPLY_BWD ? 0 : op == HH_OP_APPLY_T_BWD ? 1 : 2;
     const dim3 mg((hp * hp + 255) / 256);
-    hipLaunchKernelGGL(k_wy_mmat, mg, dim3(256), 0, st, reinterpret_cast<const float *>(base + L.gpart),
-                       L.ksg, hp, kind, reinterpret_cast<double *>(base + L.kd), nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((k_sum_parts<float>), dim3(hp * hp / 32, L.npairs), dim3(256), 0, st,
+                       reinterpret_cast<const float *>(base + L.gpart), L.ksg, (size_t)hp * hp, hp * hp,
+                       reinterpret_cast<double *>(base + L.kd));
     hipLaunchKernelGGL(k_wy_mmat2, mg, dim3(256), 0, st, reinterpret_cast<const double *>(base + L.kd), hp,
                        kind, reinterpret_cast<double *>(base + L.ma), reinterpret_cast<double *>(base + L.mb),
                        reinterpret_cast<double *>(base + L.mc));
+    {
+        const size_t ne = (size_t)s.npad * L.m;
+        hipLaunchKernelGGL((k_sum_parts<float>), dim3((unsigned)((ne + 31) / 32), 1), dim3(256), 0, st,
+                           reinterpret_cast<const float *>(base + L.part), L.ks, ne, (int)ne,
+                           reinterpret_cast<double *>(base + L.psum));
+        if (sym)
+            hipLaunchKernelGGL((k_sum_parts<float>), dim3(s.npad / 32, 1), dim3(256), 0, st,
+                               reinterpret_cast<const float *>(base + L.gx), 2 * L.ks, (size_t)s.npad,
+                               s.npad, reinterpret_cast<double *>(base + L.gxsum));
+    }
     CombineArgs ca{};
-    ca.part = reinterpret_cast<const float *>(base + L.part);
-    ca.gx = sym ? reinterpret_cast<const float *>(base + L.gx) : nullptr;
-    ca.ks = L.ks;
+    ca.part = reinterpret_cast<const double *>(base + L.psum);
+    ca.gx = sym ? reinterpret_cast<const double *>(base + L.gxsum) : nullptr;
     ca.m = L.m;
     ca.uh = reinterpret_cast<const double *>(base + L.base.uh64);
     ca.Ma = reinterpret_cast<const double *>(base + L.ma);
@@ -539,10 +571,10 @@ hh_status wy_backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, co
     ca.dlam = sym ? static_cast<float *>(dlam) : nullptr;
     ca.n = (int)n;
     ca.h = (int)h;
-    ca.hp = hp;
     ca.npad = s.npad;
     ca.kind = kind;
-    hipLaunchKernelGGL(k_wy_combine, dim3(s.npad), dim3(hp), 0, st, ca);
+    if (hp == 64) hipLaunchKernelGGL(k_wy_combine<64>, dim3(s.npad / 32), dim3(256), 0, st, ca);
+    else hipLaunchKernelGGL(k_wy_combine<128>, dim3(s.npad / 32), dim3(256), 0, st, ca);
     if (dU && h > 0)
         hipLaunchKernelGGL(k_wy_finish, dim3((unsigned)h), dim3(256), 0, st,
                            reinterpret_cast<const double *>(base + L.dv), s.npad, (int)n,

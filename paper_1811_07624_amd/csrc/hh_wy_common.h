@@ -49,6 +49,20 @@ __device__ __forceinline__ int64_t yr_index(int h, int row, int hp) {
     return ((int64_t)((q * 2 + m) * (hp >> 5) + ks) * 64 + 16 * g + c) * 8 + j;
 }
 
+// Copy read by the streaming kernel's GEMM1 (chunk-major, permuted h):
+// fragment (q, hb) holds, for lane (c, g), the 8 rows 32q + 8g + j of
+// reflector h = 32(hb/2) + 8(c/4) + 4(hb%2) + c%4, at
+//   ((q * HB + hb) * 64 + 16 g + c) * 8 + j,   HB = hp / 16.
+__device__ __forceinline__ int64_t ycs_index(int h, int row, int hp) {
+    const int hb = 2 * (h >> 5) + ((h >> 2) & 1), c = 4 * ((h >> 3) & 3) + (h & 3);
+    const int q = row >> 5, g = (row >> 3) & 3, j = row & 7;
+    return ((int64_t)(q * (hp >> 4) + hb) * 64 + 16 * g + c) * 8 + j;
+}
+// Row permutation of a 16-row MFMA block b used by the streaming kernel.
+__device__ __forceinline__ int sigma_row(int b, int r) {
+    return 32 * (b >> 1) + 8 * (r >> 2) + 4 * (b & 1) + (r & 3);
+}
+
 // Raw buffer accesses: the base address lives in a scalar descriptor, the
 // lane part of the offset in one VGPR and the row-group part in an SGPR, so
 // the unrolled loops need no per-access 64-bit addresses.  Reads past
@@ -77,6 +91,8 @@ struct WyArgs {
     int64_t ldy;
     const void *Yc;   // HP x npad, column-major reflectors (GEMM1 A operand)
     const void *Yr;   // npad x HP, row-major reflectors (GEMM2 A operand)
+    const void *Ycs;  // streaming kernel: GEMM1 operand, chunk-major (ycs_index)
+    const void *Tf;   // streaming kernel: T and T^T as 16-bit hi/lo MFMA fragments
     const float *Tm;  // HP x HP row-major
     const float *lam; // npad (SYM)
     void *coef;       // nullable: W' of pass q written to rows [q*HP, (q+1)*HP), ld = ldc
@@ -101,9 +117,12 @@ inline bool wy_shape(int64_t n, int64_t h, WyShape *s) {
     return true;
 }
 
+// Row segments of the partial Gram matrices (npad / 32 is a multiple of it).
+constexpr int kGramSeg = 16;
+
 // Workspace of the WY setup (shared by forward and backward).
 struct WyWs {
-    size_t yc, yr, nrm2, nrmraw, gram, tw, tm, lam, uh64, total;
+    size_t yc, yr, ycs, tf, nrm2, nrmraw, gram, gsum, tw, tm, lam, uh64, total;
 };
 
 inline WyWs wy_ws(const WyShape &s, int64_t n, bool with_lam, bool bwd) {
@@ -112,9 +131,12 @@ inline WyWs wy_ws(const WyShape &s, int64_t n, bool with_lam, bool bwd) {
     const size_t hp = s.hp, np = s.npad;
     w.yc = off;     off += align256(hp * np * 2);
     w.yr = off;     off += align256(hp * np * 2);
+    w.ycs = off;    off += align256(hp * np * 2);
+    w.tf = off;     off += align256(4 * hp * hp * 2);
     w.nrm2 = off;   off += align256(hp * 8);
     w.nrmraw = off; off += align256(hp * 8);
-    w.gram = off;   off += align256(hp * hp * 8);
+    w.gram = off;   off += align256(kGramSeg * hp * hp * 8);
+    w.gsum = off;   off += align256(hp * hp * 8);
     w.tw = off;     off += align256(hp * hp * 8);
     w.tm = off;     off += align256(hp * hp * 4);
     w.lam = off;    off += with_lam ? align256(np * 4) : 0;
@@ -123,11 +145,38 @@ inline WyWs wy_ws(const WyShape &s, int64_t n, bool with_lam, bool bwd) {
     return w;
 }
 
+// out[y][e] = sum over q < nq of part[(y nq + q) stride + e], e < ne, in FP64
+// and in a fixed order (8 interleaved partial sums, then added 0..7).
+// Grid (ceil(ne / 32), number of independent sums y), 256 threads.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sum_parts(const T *__restrict__ part, int nq, size_t stride,
+                                                  int ne, double *__restrict__ out) {
+    __shared__ double red[8][32];
+    const int t = threadIdx.x, e = blockIdx.x * 32 + (t & 31), grp = t >> 5;
+    const T *p = part + (size_t)blockIdx.y * nq * stride;
+    double s = 0.0;
+    if (e < ne) {
+#pragma unroll 4
+        for (int q = grp; q < nq; q += 8) s += (double)p[(size_t)q * stride + e];
+    }
+    red[grp][t & 31] = s;
+    __syncthreads();
+    if (t < 32 && e < ne) {
+        double v = 0.0;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) v += red[g][t];
+        out[(size_t)blockIdx.y * ne + e] = v;
+    }
+}
+
 // Launchers defined in hh_wy.hip.
 hipError_t wy_setup_any(bool bf, const WyShape &s, const float *U, int64_t ldu, int64_t n,
                         int64_t h, char *ws, const WyWs &w, bool want_uh, hipStream_t st);
 hipError_t wy_fill_lam(const float *lam, int n, int npad, float *out, hipStream_t st);
 hipError_t wy_main_any(bool bf, const WyShape &s, WyOp op, const WyArgs &a, hipStream_t st);
+
+// Defined in hh_wy_stream.hip.
+hipError_t wy_stream_any(bool bf, const WyShape &s, WyOp op, const WyArgs &a, hipStream_t st);
 
 // Defined in hh_wy_bwd.hip.
 size_t wy_bwd_ws_bytes(hh_op op, const WyShape &s, int64_t n, int64_t N);

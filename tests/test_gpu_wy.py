@@ -37,8 +37,11 @@ def make(n, h, N, dt, seed=0):
     return U, X
 
 
+# n * hp >= 2^19 selects the streaming kernel (tiles of 128 vectors, ragged
+# tails included); smaller shapes the register-resident one.
 SHAPES = [(4096, 64, 1000), (256, 10, 33), (512, 9, 100), (1024, 64, 50), (2048, 100, 40),
-          (8192, 128, 20), (4096, 1, 17), (1000, 7, 31), (64, 3, 5)]
+          (8192, 128, 20), (4096, 1, 17), (1000, 7, 31), (64, 3, 5), (8192, 64, 300),
+          (4096, 100, 129), (6144, 128, 257)]
 
 
 @pytest.mark.parametrize("dname", ["bf16", "f16"])
@@ -56,7 +59,8 @@ def test_wy_apply_parity(dname, n, h, N):
 
 
 @pytest.mark.parametrize("dname", ["bf16", "f16"])
-@pytest.mark.parametrize("n,h,N", [(512, 9, 64), (1024, 64, 40), (2048, 100, 16)])
+@pytest.mark.parametrize("n,h,N", [(512, 9, 64), (1024, 64, 40), (2048, 100, 16), (4096, 128, 133),
+                                   (8192, 64, 70)])
 def test_wy_sym_parity(dname, n, h, N):
     dt = DT[dname]
     U, X = make(n, h, N, dt, seed=3 * n + h)
@@ -132,7 +136,7 @@ def test_wy_matches_fused_fp32():
 from tests._util import rel_fro  # noqa: E402
 
 BSHAPES = [(512, 9, 100), (1024, 64, 50), (4096, 64, 300), (2048, 100, 40), (8192, 128, 64),
-           (256, 3, 1000), (64, 1, 7)]
+           (256, 3, 1000), (64, 1, 7), (8192, 64, 131)]
 
 
 @pytest.mark.parametrize("dname", ["bf16", "f16"])
