@@ -6,13 +6,14 @@
 // (8h+1)n for the symmetric form).  The vector never leaves the registers
 // between its single HBM read and its single HBM write.
 //
-// Mapping: LPV lanes (16 or 64) own one vector; lane c holds NC 16-byte chunks
-// at element offsets i*LPV*W + c*W (W = 4 floats or 2 doubles), so every load
-// and store instruction moves LPV*16 contiguous bytes per vector.  A dot
-// product is a per-lane partial sum followed by a DPP reduction across the
-// LPV lanes (no LDS round trip).  Reflectors (and the spectrum) are staged in
-// LDS, all at once when they fit, otherwise in chunks of hc reflectors that
-// every wave of the block walks through in lockstep.
+// Mapping: a group of LPV lanes (16, 32 or 64) owns VPL vectors; lane c holds
+// NC 16-byte chunks of each at element offsets i*LPV*W + c*W (W = 4 floats or
+// 2 doubles), so every load and store instruction moves LPV*16 contiguous
+// bytes per vector.  A dot product is a per-lane partial sum followed by a
+// DPP reduction across the LPV lanes (no LDS round trip).  Reflectors (and the
+// spectrum) are staged in LDS, all at once when they fit, otherwise in chunks
+// of hc reflectors that every wave of the block walks through in lockstep;
+// each chunk of a reflector read from LDS serves the VPL vectors of the group.
 #include <algorithm>
 
 #include "hh_internal.h"
@@ -20,22 +21,24 @@
 namespace hh {
 namespace {
 
-constexpr int kWPB = 4;          // waves per block
-constexpr int kThreads = kWPB * kWave;
 constexpr size_t kLdsBudget = 64 * 1024;
 
-template <typename T, int LPV, int NC, int OP>
-__global__ __launch_bounds__(kThreads) void k_fused_fwd(FusedFwdArgs a) {
+// PF = 1: the next vectors of the grid-stride loop are loaded while the
+// current ones are reflected (two register tiles; not for MAHAL).
+template <typename T, int LPV, int NC, int OP, int VPL, int WPB, int PF>
+__global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
     using VT = typename V16<T>::type;
     constexpr int W = V16<T>::W;
-    constexpr int E = NC * W;      // elements per lane
+    constexpr int E = NC * W;      // elements per lane and vector
     constexpr int VPW = kWave / LPV;
     constexpr int STR = LPV * W;   // element stride between a lane's chunks
+    constexpr int kThreads = WPB * kWave;
     extern __shared__ __align__(16) unsigned char smem[];
 
     const int n = a.n, h = a.h, npad = a.npad, hc = a.hc;
     T *sU = reinterpret_cast<T *>(smem);
     T *sLam = sU + (size_t)hc * npad;
+    T *sTau = sLam + npad;  // tau of the reflectors of the current chunk
     const T *gU = static_cast<const T *>(a.ut);
     const T *gTau = static_cast<const T *>(a.tau);
 
@@ -62,35 +65,40 @@ __global__ __launch_bounds__(kThreads) void k_fused_fwd(FusedFwdArgs a) {
         VT *dst = reinterpret_cast<VT *>(sU);
         const int total = cnt * (npad / W);
         for (int i = tid; i < total; i += kThreads) dst[i] = src[i];
+        for (int i = tid; i < cnt; i += kThreads) sTau[i] = gTau[k0 + i];
         __syncthreads();
         loaded = q;
     };
     if (nchunks == 1) load_chunk(0);
 
-    // One reflection of the lane's slice of the vector by reflector k.
-    auto reflect = [&](int k, T(&x)[E]) {
+    // One reflection of the lane's slices of its VPL vectors by reflector k.
+    auto reflect = [&](int k, T(&x)[VPL][E]) {
         const T *u = sU + (size_t)(k - loaded * hc) * npad + c * W;
-        T part[W];
-#pragma unroll
-        for (int v = 0; v < W; ++v) part[v] = (T)0;
         VT uv[NC];
 #pragma unroll
-        for (int i = 0; i < NC; ++i) {
-            uv[i] = *reinterpret_cast<const VT *>(u + i * STR);
+        for (int i = 0; i < NC; ++i) uv[i] = *reinterpret_cast<const VT *>(u + i * STR);
+        const T tk = sTau[k - loaded * hc];
 #pragma unroll
-            for (int v = 0; v < W; ++v) part[v] = fmat(uv[i][v], x[i * W + v], part[v]);
+        for (int v = 0; v < VPL; ++v) {
+            T part[W];
+#pragma unroll
+            for (int q = 0; q < W; ++q) part[q] = (T)0;
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+#pragma unroll
+                for (int q = 0; q < W; ++q) part[q] = fmat(uv[i][q], x[v][i * W + q], part[q]);
+            T p = part[0];
+#pragma unroll
+            for (int q = 1; q < W; ++q) p += part[q];
+            p = group_sum<LPV>(p);
+            const T coef = -p * tk;
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+#pragma unroll
+                for (int q = 0; q < W; ++q) x[v][i * W + q] = fmat(coef, uv[i][q], x[v][i * W + q]);
         }
-        T p = part[0];
-#pragma unroll
-        for (int v = 1; v < W; ++v) p += part[v];
-        p = group_sum<LPV>(p);
-        const T coef = -p * gTau[k];
-#pragma unroll
-        for (int i = 0; i < NC; ++i)
-#pragma unroll
-            for (int v = 0; v < W; ++v) x[i * W + v] = fmat(coef, uv[i][v], x[i * W + v]);
     };
-    auto run_up = [&](T(&x)[E]) {  // k = 0 .. h-1  (Q^T: H_1 first)
+    auto run_up = [&](T(&x)[VPL][E]) {  // k = 0 .. h-1  (Q^T: H_1 first)
 #pragma unroll 1
         for (int q = 0; q < nchunks; ++q) {
             load_chunk(q);
@@ -99,7 +107,7 @@ __global__ __launch_bounds__(kThreads) void k_fused_fwd(FusedFwdArgs a) {
             for (int k = q * hc; k < kend; ++k) reflect(k, x);
         }
     };
-    auto run_down = [&](T(&x)[E]) {  // k = h-1 .. 0  (Q: H_h first)
+    auto run_down = [&](T(&x)[VPL][E]) {  // k = h-1 .. 0  (Q: H_h first)
 #pragma unroll 1
         for (int q = nchunks - 1; q >= 0; --q) {
             load_chunk(q);
@@ -152,17 +160,41 @@ __global__ __launch_bounds__(kThreads) void k_fused_fwd(FusedFwdArgs a) {
         }
     };
 
-    const int64_t vpb = (int64_t)kWPB * VPW;
-    for (int64_t b0 = (int64_t)blockIdx.x * vpb; b0 < a.N; b0 += (int64_t)gridDim.x * vpb) {
-        const int64_t j = b0 + wave * VPW + row;
-        const bool valid = j < a.N;
-        T x[E];
-        load_vec(x, static_cast<const T *>(a.X), a.ldx, j, valid);
-        if constexpr (OP == F_MAHAL) {
-            T xb[E];
-            load_vec(xb, static_cast<const T *>(a.Xb), a.ldb, j, valid);
+    const int64_t vpb = (int64_t)WPB * VPW * VPL;
+    const int64_t gstride = (int64_t)gridDim.x * vpb;
+    const int64_t joff = (int64_t)(wave * VPW + row) * VPL;
+    [[maybe_unused]] T xn[PF ? VPL : 1][PF ? E : 1];
+    if constexpr (PF) {
+        const int64_t j0 = (int64_t)blockIdx.x * vpb + joff;
 #pragma unroll
-            for (int e = 0; e < E; ++e) x[e] -= xb[e];
+        for (int v = 0; v < VPL; ++v) load_vec(xn[v], static_cast<const T *>(a.X), a.ldx, j0 + v, j0 + v < a.N);
+    }
+    for (int64_t b0 = (int64_t)blockIdx.x * vpb; b0 < a.N; b0 += gstride) {
+        const int64_t j0 = b0 + joff;
+        T x[VPL][E];
+        if constexpr (PF) {
+#pragma unroll
+            for (int v = 0; v < VPL; ++v)
+#pragma unroll
+                for (int e = 0; e < E; ++e) x[v][e] = xn[v][e];
+            const int64_t jn = j0 + gstride;
+            if (b0 + gstride < a.N) {
+#pragma unroll
+                for (int v = 0; v < VPL; ++v) load_vec(xn[v], static_cast<const T *>(a.X), a.ldx, jn + v, jn + v < a.N);
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) load_vec(x[v], static_cast<const T *>(a.X), a.ldx, j0 + v, j0 + v < a.N);
+        }
+        if constexpr (OP == F_MAHAL) {
+            static_assert(!PF, "no prefetch for the two-input form");
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) {
+                T xb[E];
+                load_vec(xb, static_cast<const T *>(a.Xb), a.ldb, j0 + v, j0 + v < a.N);
+#pragma unroll
+                for (int e = 0; e < E; ++e) x[v][e] -= xb[e];
+            }
         }
         if constexpr (OP == F_APPLY) run_down(x);
         if constexpr (OP == F_APPLY_T || OP == F_SYM || OP == F_MAHAL) run_up(x);
@@ -171,45 +203,53 @@ __global__ __launch_bounds__(kThreads) void k_fused_fwd(FusedFwdArgs a) {
             for (int i = 0; i < NC; ++i) {
                 VT l = *reinterpret_cast<const VT *>(sLam + i * STR + c * W);
 #pragma unroll
-                for (int q = 0; q < W; ++q) x[i * W + q] *= l[q];
+                for (int v = 0; v < VPL; ++v)
+#pragma unroll
+                    for (int q = 0; q < W; ++q) x[v][i * W + q] *= l[q];
             }
             run_down(x);
         }
-        if constexpr (OP == F_MAHAL) {
-            T part = (T)0;
 #pragma unroll
-            for (int i = 0; i < NC; ++i) {
-                VT l = *reinterpret_cast<const VT *>(sLam + i * STR + c * W);
+        for (int v = 0; v < VPL; ++v) {
+            const int64_t j = j0 + v;
+            const bool valid = j < a.N;
+            if constexpr (OP == F_MAHAL) {
+                T part = (T)0;
 #pragma unroll
-                for (int q = 0; q < W; ++q) part = fmat(l[q] * x[i * W + q], x[i * W + q], part);
+                for (int i = 0; i < NC; ++i) {
+                    VT l = *reinterpret_cast<const VT *>(sLam + i * STR + c * W);
+#pragma unroll
+                    for (int q = 0; q < W; ++q) part = fmat(l[q] * x[v][i * W + q], x[v][i * W + q], part);
+                }
+                part = group_sum<LPV>(part);
+                if (valid && c == 0) static_cast<T *>(a.Y)[j] = part;
+            } else {
+                store_vec(x[v], static_cast<T *>(a.Y), a.ldy, j, valid);
             }
-            part = group_sum<LPV>(part);
-            if (valid && c == 0) static_cast<T *>(a.Y)[j] = part;
-        } else {
-            store_vec(x, static_cast<T *>(a.Y), a.ldy, j, valid);
         }
     }
 }
 
-template <typename T, int LPV, int NC>
+#ifndef HH_FUSED_PF
+#define HH_FUSED_PF 1
+#endif
+
+template <typename T, int LPV, int NC, int VPL = 1, int WPB = 4, int PF = 0>
 hipError_t launch_op(FusedOp op, const FusedPlan &p, const FusedFwdArgs &a, dim3 grid,
                      hipStream_t st) {
+    const dim3 block(WPB * kWave);
     switch (op) {
     case F_APPLY:
-        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_APPLY>), grid, dim3(kThreads), p.lds_bytes,
-                           st, a);
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_APPLY, VPL, WPB, PF>), grid, block, p.lds_bytes, st, a);
         break;
     case F_APPLY_T:
-        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_APPLY_T>), grid, dim3(kThreads),
-                           p.lds_bytes, st, a);
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_APPLY_T, VPL, WPB, PF>), grid, block, p.lds_bytes, st, a);
         break;
     case F_SYM:
-        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_SYM>), grid, dim3(kThreads), p.lds_bytes, st,
-                           a);
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_SYM, VPL, WPB, PF>), grid, block, p.lds_bytes, st, a);
         break;
     case F_MAHAL:
-        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_MAHAL>), grid, dim3(kThreads), p.lds_bytes,
-                           st, a);
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_MAHAL, VPL, WPB, 0>), grid, block, p.lds_bytes, st, a);
         break;
     }
     return hipGetLastError();
@@ -227,6 +267,8 @@ hipError_t dispatch(FusedOp op, const FusedPlan &p, const FusedFwdArgs &a, dim3 
         case 8: return launch_op<T, 16, 8>(op, p, a, grid, st);
         case 16: return launch_op<T, 16, 16>(op, p, a, grid, st);
         }
+    } else if (lpv == 32) {
+        if (nc == 8 && p.s.vpl == 2 && p.s.wpb == 8) return launch_op<T, 32, 8, 2, 8, HH_FUSED_PF>(op, p, a, grid, st);
     } else if (lpv == 64) {
         switch (nc) {
         case 8: return launch_op<T, 64, 8>(op, p, a, grid, st);
@@ -247,7 +289,17 @@ int next_pow2(int64_t v) {
 
 bool fused_shape(hh_dtype t, int64_t n, FusedShape *s) {
     const int W = (t == HH_F64) ? 2 : 4;
-    if (n <= 16 * W * 16) {
+    s->vpl = 1;
+    s->wpb = 4;
+    if (t == HH_F32 && n > 16 * W * 8 && n <= 32 * W * 8) {
+        // 512 < n <= 1024: 32 lanes hold two vectors each, so each reflector
+        // chunk read from LDS serves two vectors; 8 waves per block keep four
+        // waves per SIMD resident within the LDS of one compute unit
+        s->lpv = 32;
+        s->nc = 8;
+        s->vpl = 2;
+        s->wpb = 8;
+    } else if (n <= 16 * W * 16) {
         s->lpv = 16;
         s->nc = next_pow2((n + 16 * W - 1) / (16 * W));
     } else if (n <= 64 * W * 32) {
@@ -272,15 +324,20 @@ bool fused_plan(hh_dtype t, int64_t n, int64_t h, int64_t N, FusedPlan *p) {
     if (fixed + vec_bytes > kLdsBudget) return false;
     const int64_t fit = (int64_t)((kLdsBudget - fixed) / vec_bytes);
     p->hc = (int)std::max<int64_t>(1, std::min<int64_t>(h, fit));
-    p->lds_bytes = fixed + (size_t)p->hc * vec_bytes;
+    p->lds_bytes = fixed + (size_t)p->hc * (vec_bytes + es);  // reflectors and their tau
     return true;
 }
 
 hipError_t launch_fused_fwd(const FusedPlan &p, FusedOp op, const FusedFwdArgs &a,
                             hipStream_t st) {
-    const int vpb = kWPB * (kWave / p.s.lpv);
+    const int vpb = p.s.wpb * (kWave / p.s.lpv) * p.s.vpl;
     const int64_t need = (p.N + vpb - 1) / vpb;
-    const int64_t cap = (int64_t)device_cu_count() * 8;
+#ifndef HH_FUSED_GRIDMUL_PF
+#define HH_FUSED_GRIDMUL_PF 8
+#endif
+    // blocks per compute unit in the grid (the prefetching form keeps one
+    // block per compute unit resident and walks the batch in long strides)
+    const int64_t cap = (int64_t)device_cu_count() * (p.s.vpl > 1 ? HH_FUSED_GRIDMUL_PF : 8);
     const dim3 grid((unsigned)std::max<int64_t>(1, std::min(need, cap)));
     if (p.t == HH_F32) return dispatch<float>(op, p, a, grid, st);
     return dispatch<double>(op, p, a, grid, st);
