@@ -231,7 +231,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
 }
 
 #ifndef HH_FUSED_PF
-#define HH_FUSED_PF 1
+#define HH_FUSED_PF 0
 #endif
 
 template <typename T, int LPV, int NC, int VPL = 1, int WPB = 4, int PF = 0>
