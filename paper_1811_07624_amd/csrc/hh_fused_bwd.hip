@@ -12,11 +12,12 @@
 // s_{r-1} = s_r + tau a_r u, which undoes the forward update exactly up to one
 // rounding because H is its own inverse.
 //
-// One wave owns one vector (64 lanes x NC 16-byte chunks).  Reflectors are
-// read from LDS when all h fit, otherwise straight from the workspace (L2).
-// dL/du for HB
-// reflectors at a time stays in registers across all the vectors a block
-// processes; larger h takes several passes.  Each block writes its partial
+// A wave owns V vectors (64 lanes x NC 16-byte chunks each) and walks their
+// chains side by side: the V dot products of a step are independent, which
+// hides the latency of their cross-lane reductions.  Reflectors are read from
+// LDS when all h fit, otherwise straight from the workspace (L2).  dL/du for
+// HB reflectors at a time stays in registers across all the vectors a block
+// processes (shared by the V vectors of a wave); larger h takes several passes.  Each block writes its partial
 // sums; a second kernel adds the block partials in a fixed order in FP64
 // (deterministic for a given grid), scales by -tau_k and applies the chain
 // rule of the normalisation uh = u/||u||: dU = (I - uh uh^T) dL/duh / ||u||.
@@ -42,24 +43,24 @@ template <typename T, int NC> constexpr int hb_for() {
     return hb < 1 ? 1 : (hb > 16 ? 16 : hb);
 }
 
-template <typename T, int NC, int OP, bool UL>
+template <typename T, int NC, int OP, bool UL, int HB, int V>
 __global__ __launch_bounds__(kThreads) void k_fused_bwd(FusedBwdArgs a, int k0, int kcnt,
                                                        int write_dx, int do_lam, int nblocks) {
     using VT = typename V16<T>::type;
     constexpr int W = V16<T>::W;
     constexpr int E = NC * W;
     constexpr int STR = kWave * W;
-    constexpr int HB = hb_for<T, NC>();
     extern __shared__ __align__(16) unsigned char smem[];
 
     const int n = a.n, h = a.h, npad = a.npad;
     const int R = (OP == B_SYM) ? 2 * h : h;
-    // LDS: [reflectors (UL only)] [spectrum] [combine buffer] [saved dots]
+    const int RS = R > 0 ? R : 1;
+    // LDS: [reflectors (UL only)] [spectrum] [combine buffer] [saved dots] [tau]
     T *sU = reinterpret_cast<T *>(smem);
     T *sLam = sU + (UL ? (size_t)h * npad : 0);
     T *sComb = sLam + npad;
     T *sAl = sComb + npad;
-    const T *gTau = static_cast<const T *>(a.tau);
+    T *sTau = sAl + kWPB * V * RS;
     const T *uBase = UL ? sU : static_cast<const T *>(a.ut);
 
     const int tid = threadIdx.x;
@@ -76,9 +77,10 @@ __global__ __launch_bounds__(kThreads) void k_fused_bwd(FusedBwdArgs a, int k0, 
             const VT *ls = static_cast<const VT *>(a.lam);
             for (int i = tid; i < npad / W; i += kThreads) reinterpret_cast<VT *>(sLam)[i] = ls[i];
         }
+        for (int i = tid; i < h; i += kThreads) sTau[i] = static_cast<const T *>(a.tau)[i];
     }
     __syncthreads();
-    T *myAl = sAl + wave * (R > 0 ? R : 1);
+    T *myAl = sAl + wave * V * RS;  // vector v's saved dots at myAl + v * RS
 
     T acc[HB][E];
     T lacc[E];
@@ -114,38 +116,49 @@ __global__ __launch_bounds__(kThreads) void k_fused_bwd(FusedBwdArgs a, int k0, 
             for (int q = 0; q < W; ++q) v[i * W + q] = fmat(coef, uv[i][q], v[i * W + q]);
     };
     // forward sweep over one chain; up: k = r, down: k = h-1-r.  Stores a_r.
-    auto fwd_chain = [&](bool up, T(&s)[E], int abase) {
+    auto fwd_chain = [&](bool up, T(&s)[V][E], int abase) {
 #pragma unroll 1
         for (int r = 0; r < h; ++r) {
             const int k = up ? r : h - 1 - r;
             VT uv[NC];
             load_u(k, uv);
-            const T p = dot(uv, s);
-            if (lane == 0) myAl[abase + r] = p;
-            axpy(-p * gTau[k], uv, s);
+            T p[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) p[v] = dot(uv, s[v]);
+            const T t = sTau[k];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                if (lane == 0) myAl[v * RS + abase + r] = p[v];
+                axpy(-p[v] * t, uv, s[v]);
+            }
         }
     };
     // One reverse step for reflector k at chain position r: rebuilds s_{r-1},
     // propagates g and, when ACC, accumulates dL/du into acc[B].
-    auto rev_step = [&](auto accb, int k, int r, T(&s)[E], T(&g)[E], int abase) {
+    auto rev_step = [&](auto accb, int k, int r, T(&s)[V][E], T(&g)[V][E], int abase) {
         constexpr int B = decltype(accb)::value;
         VT uv[NC];
         load_u(k, uv);
-        const T beta = dot(uv, g);
-        const T p = myAl[abase + r];
-        const T t = gTau[k];
-        axpy(t * p, uv, s);  // s <- s_{r-1}
-        if constexpr (B >= 0) {
+        T beta[V];
 #pragma unroll
-            for (int e = 0; e < E; ++e)
-                acc[B][e] = fmat(p, g[e], fmat(beta, s[e], acc[B][e]));
+        for (int v = 0; v < V; ++v) beta[v] = dot(uv, g[v]);
+        const T t = sTau[k];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const T p = myAl[v * RS + abase + r];
+            axpy(t * p, uv, s[v]);  // s <- s_{r-1}
+            if constexpr (B >= 0) {
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    acc[B][e] = fmat(p, g[v][e], fmat(beta[v], s[v][e], acc[B][e]));
+            }
+            axpy(-t * beta[v], uv, g[v]);
         }
-        axpy(-t * beta, uv, g);
     };
     using NoAcc = std::integral_constant<int, -1>;
     // reverse sweep over one chain.  The accumulated window k0 .. k0+kcnt-1 is
     // a contiguous run of steps, walked with compile-time accumulator slots.
-    auto rev_chain = [&](bool up, T(&s)[E], T(&g)[E], int abase) {
+    auto rev_chain = [&](bool up, T(&s)[V][E], T(&g)[V][E], int abase) {
         const int kw = k0 + kcnt;
         if (up) {  // reverse visits k = h-1 .. 0, position r = k
 #pragma unroll 1
@@ -211,66 +224,85 @@ __global__ __launch_bounds__(kThreads) void k_fused_bwd(FusedBwdArgs a, int k0, 
     };
     auto lam_chunk = [&](int i) { return *reinterpret_cast<const VT *>(sLam + i * STR + lane * W); };
 
-    for (int64_t b0 = (int64_t)blockIdx.x * kWPB; b0 < a.N; b0 += (int64_t)gridDim.x * kWPB) {
-        const int64_t j = b0 + wave;
-        const bool valid = j < a.N;
-        T s[E], g[E];
-        load_vec(s, static_cast<const T *>(a.X), a.ldx, j, valid);
-        if constexpr (OP == B_MAHAL) {
-            load_vec(g, static_cast<const T *>(a.Xb), a.ldb, j, valid);
+    const int64_t vpb = (int64_t)kWPB * V;
+    for (int64_t b0 = (int64_t)blockIdx.x * vpb; b0 < a.N; b0 += (int64_t)gridDim.x * vpb) {
+        const int64_t j0 = b0 + (int64_t)wave * V;
+        T s[V][E], g[V][E];
 #pragma unroll
-            for (int e = 0; e < E; ++e) s[e] -= g[e];
+        for (int v = 0; v < V; ++v) load_vec(s[v], static_cast<const T *>(a.X), a.ldx, j0 + v, j0 + v < a.N);
+        if constexpr (OP == B_MAHAL) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                load_vec(g[v], static_cast<const T *>(a.Xb), a.ldb, j0 + v, j0 + v < a.N);
+#pragma unroll
+                for (int e = 0; e < E; ++e) s[v][e] -= g[v][e];
+            }
         }
         if constexpr (OP == B_APPLY || OP == B_APPLY_T) {
             constexpr bool up = (OP == B_APPLY_T);
             fwd_chain(up, s, 0);
-            load_vec(g, static_cast<const T *>(a.G), a.ldg, j, valid);
+#pragma unroll
+            for (int v = 0; v < V; ++v) load_vec(g[v], static_cast<const T *>(a.G), a.ldg, j0 + v, j0 + v < a.N);
             rev_chain(up, s, g, 0);
         } else if constexpr (OP == B_SYM) {
             fwd_chain(true, s, 0);
-            T z[E];
+            T z[V][E];
 #pragma unroll
             for (int i = 0; i < NC; ++i) {
                 const VT l = lam_chunk(i);
 #pragma unroll
-                for (int q = 0; q < W; ++q) {
-                    z[i * W + q] = s[i * W + q];
-                    s[i * W + q] *= l[q];
-                }
+                for (int v = 0; v < V; ++v)
+#pragma unroll
+                    for (int q = 0; q < W; ++q) {
+                        z[v][i * W + q] = s[v][i * W + q];
+                        s[v][i * W + q] *= l[q];
+                    }
             }
             fwd_chain(false, s, h);
-            load_vec(g, static_cast<const T *>(a.G), a.ldg, j, valid);
+#pragma unroll
+            for (int v = 0; v < V; ++v) load_vec(g[v], static_cast<const T *>(a.G), a.ldg, j0 + v, j0 + v < a.N);
             rev_chain(false, s, g, h);  // g = Q^T dY
 #pragma unroll
             for (int i = 0; i < NC; ++i) {
                 const VT l = lam_chunk(i);
 #pragma unroll
-                for (int q = 0; q < W; ++q) {
-                    lacc[i * W + q] = fmat(g[i * W + q], z[i * W + q], lacc[i * W + q]);
-                    g[i * W + q] *= l[q];
-                    s[i * W + q] = z[i * W + q];
-                }
+                for (int v = 0; v < V; ++v)
+#pragma unroll
+                    for (int q = 0; q < W; ++q) {
+                        lacc[i * W + q] = fmat(g[v][i * W + q], z[v][i * W + q], lacc[i * W + q]);
+                        g[v][i * W + q] *= l[q];
+                        s[v][i * W + q] = z[v][i * W + q];
+                    }
             }
             rev_chain(true, s, g, 0);
         } else {  // B_MAHAL
             fwd_chain(true, s, 0);
-            const T w = valid ? static_cast<const T *>(a.G)[j] : (T)0;
 #pragma unroll
-            for (int i = 0; i < NC; ++i) {
-                const VT l = lam_chunk(i);
+            for (int v = 0; v < V; ++v) {
+                const T w = (j0 + v < a.N) ? static_cast<const T *>(a.G)[j0 + v] : (T)0;
 #pragma unroll
-                for (int q = 0; q < W; ++q) {
-                    const T z = s[i * W + q];
-                    lacc[i * W + q] = fmat(w * z, z, lacc[i * W + q]);
-                    g[i * W + q] = (T)2 * w * l[q] * z;
+                for (int i = 0; i < NC; ++i) {
+                    const VT l = lam_chunk(i);
+#pragma unroll
+                    for (int q = 0; q < W; ++q) {
+                        const T z = s[v][i * W + q];
+                        lacc[i * W + q] = fmat(w * z, z, lacc[i * W + q]);
+                        g[v][i * W + q] = (T)2 * w * l[q] * z;
+                    }
                 }
             }
             rev_chain(true, s, g, 0);
         }
-        if (write_dx && valid) {
-            if (a.dX) store_vec(g, (T)1, static_cast<T *>(a.dX), a.lddx, j);
-            if constexpr (OP == B_MAHAL)
-                if (a.dXb) store_vec(g, (T)-1, static_cast<T *>(a.dXb), a.lddx, j);
+        if (write_dx) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int64_t j = j0 + v;
+                if (j < a.N) {
+                    if (a.dX) store_vec(g[v], (T)1, static_cast<T *>(a.dX), a.lddx, j);
+                    if constexpr (OP == B_MAHAL)
+                        if (a.dXb) store_vec(g[v], (T)-1, static_cast<T *>(a.dXb), a.lddx, j);
+                }
+            }
         }
     }
 
@@ -352,10 +384,24 @@ __global__ __launch_bounds__(256) void k_bwd_finish(const double *__restrict__ r
     }
 }
 
+// Vectors per wave: HH_BWD_VPW when a vector takes at most 8 registers per
+// lane, else one.
+#ifndef HH_BWD_VPW
+#define HH_BWD_VPW 4
+#endif
+template <typename T, int NC> constexpr int vpw_for() {
+    return NC * V16<T>::W * (int)(sizeof(T) / 4) <= 8 ? HH_BWD_VPW : 1;
+}
+int bwd_vpw(const FusedPlan &p) {
+    const int regs = p.s.nc * ((p.t == HH_F64) ? 2 : 4) * ((p.t == HH_F64) ? 2 : 1);
+    return regs <= 8 ? HH_BWD_VPW : 1;
+}
+
 size_t lds_small(hh_op op, const FusedPlan &p) {
     const size_t es = (p.t == HH_F64) ? 8 : 4;
     const size_t R = (op == HH_OP_SYM_BWD) ? 2 * (size_t)p.h : (size_t)p.h;
-    return 2 * (size_t)p.s.npad * es + kWPB * std::max<size_t>(R, 1) * es;
+    return 2 * (size_t)p.s.npad * es + (size_t)kWPB * bwd_vpw(p) * std::max<size_t>(R, 1) * es +
+           std::max<size_t>((size_t)p.h, 1) * es;
 }
 bool refl_in_lds(hh_op op, const FusedPlan &p) {
     const size_t es = (p.t == HH_F64) ? 8 : 4;
@@ -372,46 +418,50 @@ size_t partial_bytes(const FusedPlan &p, int nb) {
 }
 
 int bwd_blocks(const FusedPlan &p) {
-    const int64_t need = (p.N + kWPB - 1) / kWPB;
+    const int64_t vpb = (int64_t)kWPB * bwd_vpw(p);
+    const int64_t need = (p.N + vpb - 1) / vpb;
     const int64_t cap = (int64_t)device_cu_count() * 2;
     return (int)std::max<int64_t>(1, std::min(need, cap));
 }
 
-template <typename T, int NC, bool UL>
+template <typename T, int NC, bool UL, int HB, int V>
 hipError_t launch_main(hh_op op, const FusedPlan &p, const FusedBwdArgs &a, dim3 grid,
                        size_t lds, int k0, int kcnt, int wdx, int dl, int nb, hipStream_t st) {
     switch (op) {
     case HH_OP_APPLY_BWD:
-        hipLaunchKernelGGL((k_fused_bwd<T, NC, B_APPLY, UL>), grid, dim3(kThreads), lds, st, a, k0,
+        hipLaunchKernelGGL((k_fused_bwd<T, NC, B_APPLY, UL, HB, V>), grid, dim3(kThreads), lds, st, a, k0,
                            kcnt, wdx, dl, nb);
         break;
     case HH_OP_APPLY_T_BWD:
-        hipLaunchKernelGGL((k_fused_bwd<T, NC, B_APPLY_T, UL>), grid, dim3(kThreads), lds, st, a, k0,
+        hipLaunchKernelGGL((k_fused_bwd<T, NC, B_APPLY_T, UL, HB, V>), grid, dim3(kThreads), lds, st, a, k0,
                            kcnt, wdx, dl, nb);
         break;
     case HH_OP_SYM_BWD:
-        hipLaunchKernelGGL((k_fused_bwd<T, NC, B_SYM, UL>), grid, dim3(kThreads), lds, st, a, k0,
+        hipLaunchKernelGGL((k_fused_bwd<T, NC, B_SYM, UL, HB, V>), grid, dim3(kThreads), lds, st, a, k0,
                            kcnt, wdx, dl, nb);
         break;
     default:
-        hipLaunchKernelGGL((k_fused_bwd<T, NC, B_MAHAL, UL>), grid, dim3(kThreads), lds, st, a, k0,
+        hipLaunchKernelGGL((k_fused_bwd<T, NC, B_MAHAL, UL, HB, V>), grid, dim3(kThreads), lds, st, a, k0,
                            kcnt, wdx, dl, nb);
         break;
     }
     return hipGetLastError();
 }
 
-template <typename T, int NC>
-hipError_t run_bwd(hh_op op, const FusedPlan &p, const FusedBwdArgs &a, hipStream_t st) {
-    constexpr int HB = hb_for<T, NC>();
+// ULO: only the form with the reflectors in LDS is instantiated.
+template <typename T, int NC, int HB, bool ULO = false>
+hipError_t run_bwd_hb(hh_op op, const FusedPlan &p, const FusedBwdArgs &a, hipStream_t st) {
+    constexpr int V = vpw_for<T, NC>();
     const int nb = bwd_blocks(p);
     const size_t lds = lds_bytes_for(op, p);
     const dim3 grid(nb);
     const int h = (int)p.h;
     const bool ul = refl_in_lds(op, p);
     auto go = [&](int k0, int cnt, int wdx, int dl) {
-        return ul ? launch_main<T, NC, true>(op, p, a, grid, lds, k0, cnt, wdx, dl, nb, st)
-                  : launch_main<T, NC, false>(op, p, a, grid, lds, k0, cnt, wdx, dl, nb, st);
+        if constexpr (ULO) return launch_main<T, NC, true, HB, V>(op, p, a, grid, lds, k0, cnt, wdx, dl, nb, st);
+        else
+            return ul ? launch_main<T, NC, true, HB, V>(op, p, a, grid, lds, k0, cnt, wdx, dl, nb, st)
+                      : launch_main<T, NC, false, HB, V>(op, p, a, grid, lds, k0, cnt, wdx, dl, nb, st);
     };
     if (!a.dU || h == 0) {
         hipError_t e = go(0, 0, 1, 1);
@@ -445,6 +495,19 @@ hipError_t run_bwd(hh_op op, const FusedPlan &p, const FusedBwdArgs &a, hipStrea
         return hipGetLastError();
     }
     return hipSuccess;
+}
+
+// Accumulator window: 10 slots when h <= 10 (the reflectors then always fit
+// in LDS) and the registers allow 16, else what the registers allow.
+template <typename T, int NC>
+hipError_t run_bwd(hh_op op, const FusedPlan &p, const FusedBwdArgs &a, hipStream_t st) {
+    constexpr int HBM = hb_for<T, NC>();
+    if constexpr (HBM >= 16) {
+        if (p.h <= 10 && refl_in_lds(op, p)) return run_bwd_hb<T, NC, 10, true>(op, p, a, st);
+        return run_bwd_hb<T, NC, 16>(op, p, a, st);
+    } else {
+        return run_bwd_hb<T, NC, HBM>(op, p, a, st);
+    }
 }
 
 template <typename T>

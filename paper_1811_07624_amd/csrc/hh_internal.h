@@ -99,6 +99,30 @@ template <int LPV, typename T> __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
+// out[y][e] = sum over q < nq of part[(y nq + q) stride + e], e < ne, in FP64
+// and in a fixed order (8 interleaved partial sums, then added 0..7).
+// Grid (ceil(ne / 32), number of independent sums y), 256 threads.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sum_parts(const T *__restrict__ part, int nq, size_t stride,
+                                                  int ne, double *__restrict__ out) {
+    __shared__ double red[8][32];
+    const int t = threadIdx.x, e = blockIdx.x * 32 + (t & 31), grp = t >> 5;
+    const T *p = part + (size_t)blockIdx.y * nq * stride;
+    double s = 0.0;
+    if (e < ne) {
+#pragma unroll 4
+        for (int q = grp; q < nq; q += 8) s += (double)p[(size_t)q * stride + e];
+    }
+    red[grp][t & 31] = s;
+    __syncthreads();
+    if (t < 32 && e < ne) {
+        double v = 0.0;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) v += red[g][t];
+        out[(size_t)blockIdx.y * ne + e] = v;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Kernel selection for the fused (sequential-reflector) kernels: LPV lanes
 // own one vector, each lane NC 16-byte chunks of it; npad = NC*LPV*W >= n.

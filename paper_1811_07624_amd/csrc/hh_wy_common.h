@@ -145,30 +145,6 @@ inline WyWs wy_ws(const WyShape &s, int64_t n, bool with_lam, bool bwd) {
     return w;
 }
 
-// out[y][e] = sum over q < nq of part[(y nq + q) stride + e], e < ne, in FP64
-// and in a fixed order (8 interleaved partial sums, then added 0..7).
-// Grid (ceil(ne / 32), number of independent sums y), 256 threads.
-template <typename T>
-__global__ __launch_bounds__(256) void k_sum_parts(const T *__restrict__ part, int nq, size_t stride,
-                                                  int ne, double *__restrict__ out) {
-    __shared__ double red[8][32];
-    const int t = threadIdx.x, e = blockIdx.x * 32 + (t & 31), grp = t >> 5;
-    const T *p = part + (size_t)blockIdx.y * nq * stride;
-    double s = 0.0;
-    if (e < ne) {
-#pragma unroll 4
-        for (int q = grp; q < nq; q += 8) s += (double)p[(size_t)q * stride + e];
-    }
-    red[grp][t & 31] = s;
-    __syncthreads();
-    if (t < 32 && e < ne) {
-        double v = 0.0;
-#pragma unroll
-        for (int g = 0; g < 8; ++g) v += red[g][t];
-        out[(size_t)blockIdx.y * ne + e] = v;
-    }
-}
-
 // Launchers defined in hh_wy.hip.
 hipError_t wy_setup_any(bool bf, const WyShape &s, const float *U, int64_t ldu, int64_t n,
                         int64_t h, char *ws, const WyWs &w, bool want_uh, hipStream_t st);
