@@ -21,7 +21,8 @@
 namespace hh {
 namespace {
 
-constexpr size_t kLdsBudget = 64 * 1024;
+constexpr size_t kLdsBudget = 64 * 1024;       // several blocks per compute unit
+constexpr size_t kLdsBudgetWide = 144 * 1024;  // one 8-wave block per compute unit
 
 // PF = 1: the next vectors of the grid-stride loop are loaded while the
 // current ones are reflected (two register tiles; not for MAHAL).
@@ -186,14 +187,35 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
 #pragma unroll
             for (int v = 0; v < VPL; ++v) load_vec(x[v], static_cast<const T *>(a.X), a.ldx, j0 + v, j0 + v < a.N);
         }
-        if constexpr (OP == F_MAHAL) {
+        if constexpr (OP == F_MAHAL && VPL == 1) {
             static_assert(!PF, "no prefetch for the two-input form");
+            T xb[E];
+            load_vec(xb, static_cast<const T *>(a.Xb), a.ldb, j0, j0 < a.N);
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[0][e] -= xb[e];
+        } else if constexpr (OP == F_MAHAL) {
+            static_assert(!PF, "no prefetch for the two-input form");
+            // x - xb one 16-byte chunk at a time (keeps the second input's
+            // registers to one chunk when a lane holds two vectors)
+            const T *Xb = static_cast<const T *>(a.Xb);
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
-                T xb[E];
-                load_vec(xb, static_cast<const T *>(a.Xb), a.ldb, j0 + v, j0 + v < a.N);
+                const int64_t j = j0 + v;
+                const bool valid = j < a.N;
 #pragma unroll
-                for (int e = 0; e < E; ++e) x[v][e] -= xb[e];
+                for (int i = 0; i < NC; ++i) {
+                    const int e0 = i * STR + c * W;
+                    if (a.vec_ok) {
+                        VT b = {};
+                        if (valid && e0 < n) b = *reinterpret_cast<const VT *>(Xb + j * a.ldb + e0);
+#pragma unroll
+                        for (int q = 0; q < W; ++q) x[v][i * W + q] -= b[q];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < W; ++q)
+                            if (valid && e0 + q < n) x[v][i * W + q] -= Xb[j * a.ldb + e0 + q];
+                    }
+                }
             }
         }
         if constexpr (OP == F_APPLY) run_down(x);
@@ -271,8 +293,8 @@ hipError_t dispatch(FusedOp op, const FusedPlan &p, const FusedFwdArgs &a, dim3 
         if (nc == 8 && p.s.vpl == 2 && p.s.wpb == 8) return launch_op<T, 32, 8, 2, 8, HH_FUSED_PF>(op, p, a, grid, st);
     } else if (lpv == 64) {
         switch (nc) {
-        case 8: return launch_op<T, 64, 8>(op, p, a, grid, st);
-        case 16: return launch_op<T, 64, 16>(op, p, a, grid, st);
+        case 8: return launch_op<T, 64, 8, 2, 8>(op, p, a, grid, st);
+        case 16: return launch_op<T, 64, 16, 2, 8>(op, p, a, grid, st);
         case 32: return launch_op<T, 64, 32>(op, p, a, grid, st);
         }
     }
@@ -305,6 +327,13 @@ bool fused_shape(hh_dtype t, int64_t n, FusedShape *s) {
     } else if (n <= 64 * W * 32) {
         s->lpv = 64;
         s->nc = std::max(8, next_pow2((n + 64 * W - 1) / (64 * W)));
+        if (s->nc <= 16) {
+            // two vectors per wave and 8-wave blocks: each reflector chunk
+            // staged in LDS (up to 144 KB, one block per compute unit) serves
+            // 16 vectors
+            s->vpl = 2;
+            s->wpb = 8;
+        }
     } else {
         return false;
     }
@@ -321,8 +350,9 @@ bool fused_plan(hh_dtype t, int64_t n, int64_t h, int64_t N, FusedPlan *p) {
     const size_t es = (t == HH_F64) ? 8 : 4;
     const size_t vec_bytes = (size_t)p->s.npad * es;
     const size_t fixed = vec_bytes;  // spectrum
-    if (fixed + vec_bytes > kLdsBudget) return false;
-    const int64_t fit = (int64_t)((kLdsBudget - fixed) / vec_bytes);
+    const size_t budget = (p->s.lpv == 64 && p->s.wpb == 8) ? kLdsBudgetWide : kLdsBudget;
+    if (fixed + vec_bytes > budget) return false;
+    const int64_t fit = (int64_t)((budget - fixed) / vec_bytes);
     p->hc = (int)std::max<int64_t>(1, std::min<int64_t>(h, fit));
     p->lds_bytes = fixed + (size_t)p->hc * (vec_bytes + es);  // reflectors and their tau
     return true;

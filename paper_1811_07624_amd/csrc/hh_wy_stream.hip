@@ -179,6 +179,30 @@ __global__ __launch_bounds__(kST, 2 * BPC) void k_wy_stream(WyArgs a) {
             }
         }
     };
+    // Both corrections of the symmetric form's last phase from one read of
+    // the GEMM2 operand: o[cb][m] = Yr(qi, m) Z1, o2[cb][m] = Yr(qi, m) Z2.
+    auto gemm2x2 = [&](const unsigned char *sl, int qi, const v8(&z)[2][KS][NCB], const v8(&z2)[2][KS][NCB],
+                       f32x4(&o)[NCB][2], f32x4(&o2)[NCB][2]) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+            o[cb][0] = o[cb][1] = o2[cb][0] = o2[cb][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const v8 a0 = lds_frag(sl + YCS_B + ((qi * 2 + 0) * KS + ks) * 1024);
+            const v8 a1 = lds_frag(sl + YCS_B + ((qi * 2 + 1) * KS + ks) * 1024);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                o[cb][0] = E::mfma(a0, z[0][ks][cb], o[cb][0]);
+                o[cb][0] = E::mfma(a0, z[1][ks][cb], o[cb][0]);
+                o[cb][1] = E::mfma(a1, z[0][ks][cb], o[cb][1]);
+                o[cb][1] = E::mfma(a1, z[1][ks][cb], o[cb][1]);
+                o2[cb][0] = E::mfma(a0, z2[0][ks][cb], o2[cb][0]);
+                o2[cb][0] = E::mfma(a0, z2[1][ks][cb], o2[cb][0]);
+                o2[cb][1] = E::mfma(a1, z2[0][ks][cb], o2[cb][1]);
+                o2[cb][1] = E::mfma(a1, z2[1][ks][cb], o2[cb][1]);
+            }
+        }
+    };
     // GEMM1 step of chunk row block qi: acc[hb][cb] += Ycs(qi, hb)^T b[cb]
     auto gemm1 = [&](const unsigned char *sl, int qi, const v8(&b)[NCB], f32x4(&acc)[HB][NCB]) {
 #pragma unroll
@@ -304,8 +328,7 @@ __global__ __launch_bounds__(kST, 2 * BPC) void k_wy_stream(WyArgs a) {
 #pragma unroll
                     for (int qi = 0; qi < QC; ++qi) {
                         f32x4 o[NCB][2], o2[NCB][2];
-                        gemm2(sl, qi, z1, o);
-                        gemm2(sl, qi, z2, o2);
+                        gemm2x2(sl, qi, z1, z2, o, o2);
 #pragma unroll
                         for (int cb = 0; cb < NCB; ++cb) {
                             const v8 sv = scaled(sl, qi, xc[qi][cb], o[cb]);

@@ -92,9 +92,9 @@ def test_wy_edge_cases():
     assert rel_rows(host(P.apply_raw(U, X, compute=dt)), ref) < TOL16
 
 
-def test_wy_ld_and_in_place():
+@pytest.mark.parametrize("n,h,N", [(256, 12, 40), (8192, 64, 37)])  # resident / streaming kernel
+def test_wy_ld_and_in_place(n, h, N):
     dt = torch.bfloat16
-    n, h, N = 256, 12, 40
     U, X = make(n, h, N, dt)
     big = torch.zeros((N, n + 16), dtype=dt, device=dev())
     big[:, :n] = X
@@ -197,6 +197,34 @@ def test_wy_bwd_edge_cases():
     assert torch.count_nonzero(dU[1]) == 0
     _, rdU = oracle.apply_bwd(host(U), host(X), host(G))
     assert rel_fro(host(dU), rdU) < TOL16
+
+
+def test_wy_stream_sym_ld_in_place():
+    """Streaming kernel (n * hp >= 2^19): leading dimensions larger than n,
+    in-place symmetric form, and the backward reading strided inputs."""
+    dt = torch.float16
+    n, h, N = 4096, 120, 50
+    U, X = make(n, h, N, dt, seed=11)
+    lam = torch.tensor(synth.eig_loguniform(n, seed=4), dtype=torch.float32, device=dev())
+    big = torch.zeros((N, n + 40), dtype=dt, device=dev())
+    big[:, :n] = X
+    ref = oracle.sym(host(U), host(lam), host(X))
+    Y = P.sym_raw(U, lam, big[:, :n], compute=dt)
+    assert rel_rows(host(Y), ref) < TOL16
+    P.sym_raw(U, lam, big[:, :n], compute=dt, out=big[:, :n])
+    assert rel_rows(host(big[:, :n]), ref) < TOL16
+    assert torch.count_nonzero(big[:, n:]) == 0
+    Gb = torch.zeros((N, n + 8), dtype=dt, device=dev())
+    G = torch.tensor(synth.gaussian((N, n), seed=5, stream=synth.STREAM_G), dtype=torch.float32,
+                     device=dev()).to(dt)
+    Gb[:, :n] = G
+    Xb = torch.zeros((N, n + 16), dtype=dt, device=dev())
+    Xb[:, :n] = X
+    dX, dU, dlam = P.sym_bwd_raw(U, lam, Xb[:, :n], Gb[:, :n], compute=dt)
+    rdX, rdU, rdlam = oracle.sym_bwd(host(U), host(lam), host(X), host(G))
+    assert rel_rows(host(dX), rdX) < TOL16
+    assert rel_fro(host(dU), rdU) < TOL16
+    assert rel_fro(host(dlam), rdlam) < TOL16
 
 
 def test_wy_bwd_deterministic():
