@@ -28,7 +28,14 @@
 namespace hh {
 namespace {
 
-constexpr int kT = 512;  // threads of the product kernels
+constexpr int kT = 512;  // threads of the coefficient Gram kernel
+#ifndef HH_RANK_ROWS
+#define HH_RANK_ROWS 256
+#endif
+// Rows per block of the rank-N product (32 per wave).  Measured on MI355X:
+// 128 or 64 rows (two or four blocks per compute unit) lose more to the
+// repeated coefficient reads than they gain in overlap.
+constexpr int kRankRows = HH_RANK_ROWS;
 
 struct RankArgs {
     const void *D[2];   // G, X (n x N, 16-bit, column-major)
@@ -42,23 +49,26 @@ struct RankArgs {
 };
 
 // out[s][r][m] = sum over the vectors j of split s of G[r][j] C0[m][j] + X[r][j] C1[m][j].
-// Block: rows [256 bx, 256 bx + 256), wave w owns 32 of them, all m columns.
-template <typename E, int MB>
-__global__ __launch_bounds__(kT) void k_wy_rank(RankArgs a) {
+// Block of NW waves: rows [RB bx, RB bx + RB), RB = 32 NW; wave w owns 32 of
+// them, all m columns.
+template <typename E, int MB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_wy_rank(RankArgs a) {
     using el = typename E::elem;
     using v8 = typename E::vec8;
+    constexpr int T = 64 * NW;    // threads
+    constexpr int RB = 32 * NW;   // rows per block
     constexpr int M = 16 * MB;
-    constexpr int RS = 256 + 4;   // LDS row stride of a staged vector slice (elements)
+    constexpr int RS = RB + 4;    // LDS row stride of a staged vector slice (elements)
     constexpr int CSd = 32 + 8;   // LDS row stride of a staged coefficient row
-    constexpr int CD = 4;         // 16-byte data chunks per thread per step
-    constexpr int CC = (2 * M * 4 + kT - 1) / kT;
+    constexpr int CD = 4;         // 16-byte data chunks per thread per step (8 RB of them)
+    constexpr int CC = (2 * M * 4 + T - 1) / T;
     extern __shared__ __align__(16) unsigned char smem[];
     el *sD = reinterpret_cast<el *>(smem);      // [2][32][RS]
     el *sC = sD + 2 * 32 * RS;                  // [2][M][CSd]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6, c = lane & 15, g = lane >> 4;
-    const int rb0 = blockIdx.x * 256;
+    const int rb0 = blockIdx.x * RB;
     const int64_t jb = (int64_t)blockIdx.y * a.chunk;
     const int64_t je = jb + a.chunk < a.N ? jb + a.chunk : a.N;
     const el *D0 = static_cast<const el *>(a.D[0]);
@@ -77,8 +87,8 @@ __global__ __launch_bounds__(kT) void k_wy_rank(RankArgs a) {
     auto load_step = [&](int64_t j0) {
 #pragma unroll
         for (int t = 0; t < CD; ++t) {
-            const int ci = tid + kT * t;
-            const int src = ci >> 10, cc = ci & 1023, j = cc >> 5, rcn = cc & 31;
+            const int ci = tid + T * t;
+            const int src = ci / (4 * RB), cc = ci % (4 * RB), j = cc / (RB / 8), rcn = cc % (RB / 8);
             const int row = rb0 + 8 * rcn;
             const int64_t jj = j0 + j;
             v8 v = {};
@@ -90,7 +100,7 @@ __global__ __launch_bounds__(kT) void k_wy_rank(RankArgs a) {
         }
 #pragma unroll
         for (int t = 0; t < CC; ++t) {
-            const int ci = tid + kT * t;
+            const int ci = tid + T * t;
             v8 v = {};
             if (ci < 2 * M * 4) {
                 const int src = ci / (M * 4), cc = ci % (M * 4), mr = cc >> 2, jc = cc & 3;
@@ -105,8 +115,8 @@ __global__ __launch_bounds__(kT) void k_wy_rank(RankArgs a) {
     auto store_step = [&]() {
 #pragma unroll
         for (int t = 0; t < CD; ++t) {
-            const int ci = tid + kT * t;
-            const int src = ci >> 10, cc = ci & 1023, j = cc >> 5, rcn = cc & 31;
+            const int ci = tid + T * t;
+            const int src = ci / (4 * RB), cc = ci % (4 * RB), j = cc / (RB / 8), rcn = cc % (RB / 8);
             typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
             const u64x2 b = __builtin_bit_cast(u64x2, rd[t]);
             unsigned long long *dst =
@@ -116,7 +126,7 @@ __global__ __launch_bounds__(kT) void k_wy_rank(RankArgs a) {
         }
 #pragma unroll
         for (int t = 0; t < CC; ++t) {
-            const int ci = tid + kT * t;
+            const int ci = tid + T * t;
             if (ci < 2 * M * 4) {
                 const int src = ci / (M * 4), cc = ci % (M * 4), mr = cc >> 2, jc = cc & 3;
                 *reinterpret_cast<v8 *>(sC + (src * M + mr) * CSd + 8 * jc) = rc[t];
@@ -146,7 +156,7 @@ __global__ __launch_bounds__(kT) void k_wy_rank(RankArgs a) {
             }
         }
         if (a.gx) {
-            const int row = tid & 255, half = tid >> 8;
+            const int row = tid % RB, half = tid / RB;
 #pragma unroll
             for (int j = 0; j < 16; ++j)
                 gxa += (float)sD[(16 * half + j) * RS + row] * (float)sD[(32 + 16 * half + j) * RS + row];
@@ -160,7 +170,7 @@ __global__ __launch_bounds__(kT) void k_wy_rank(RankArgs a) {
             *reinterpret_cast<f32x4 *>(a.out + ((size_t)blockIdx.y * a.npad + r) * M + 16 * mb + 4 * g) =
                 acc[rbk][mb];
     }
-    if (a.gx) a.gx[((size_t)blockIdx.y * 2 + (tid >> 8)) * a.npad + rb0 + (tid & 255)] = gxa;
+    if (a.gx) a.gx[((size_t)blockIdx.y * 2 + tid / RB) * a.npad + rb0 + tid % RB] = gxa;
 }
 
 struct GramArgs {
@@ -369,7 +379,7 @@ BwdLayout bwd_layout(hh_op op, const WyShape &s, int64_t n, int64_t N) {
     L.base = wy_ws(s, n, sym, true);
     L.ldc = std::max<int64_t>(32, (N + 31) / 32 * 32);
     L.m = sym ? 2 * s.hp : s.hp;
-    const int rowblocks = s.npad / 256;
+    const int rowblocks = s.npad / kRankRows;
     const int64_t steps = std::max<int64_t>(1, (N + 31) / 32);
     L.ks = (int)std::min<int64_t>(steps, std::max(1, 2 * device_cu_count() / rowblocks));
     L.chunk = (steps + L.ks - 1) / L.ks * 32;
@@ -414,12 +424,13 @@ hipError_t launch_products(const WyShape &s, const BwdLayout &L, char *ws, const
     ra.npad = s.npad;
     ra.N = N;
     ra.chunk = L.chunk;
-    const dim3 rgrid(s.npad / 256, L.ks);
-    const size_t rlds = (size_t)(2 * 32 * (256 + 4) + 2 * L.m * (32 + 8)) * 2;
+    const dim3 rgrid(s.npad / kRankRows, L.ks);
+    const size_t rlds = (size_t)(2 * 32 * (kRankRows + 4) + 2 * L.m * (32 + 8)) * 2;
+    const dim3 rblock(2 * kRankRows);
     switch (L.m) {
-    case 64: hipLaunchKernelGGL((k_wy_rank<E, 4>), rgrid, dim3(kT), rlds, st, ra); break;
-    case 128: hipLaunchKernelGGL((k_wy_rank<E, 8>), rgrid, dim3(kT), rlds, st, ra); break;
-    default: hipLaunchKernelGGL((k_wy_rank<E, 16>), rgrid, dim3(kT), rlds, st, ra); break;
+    case 64: hipLaunchKernelGGL((k_wy_rank<E, 4, kRankRows / 32>), rgrid, rblock, rlds, st, ra); break;
+    case 128: hipLaunchKernelGGL((k_wy_rank<E, 8, kRankRows / 32>), rgrid, rblock, rlds, st, ra); break;
+    default: hipLaunchKernelGGL((k_wy_rank<E, 16, kRankRows / 32>), rgrid, rblock, rlds, st, ra); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
