@@ -188,7 +188,8 @@ __global__ __launch_bounds__(256) void k_wy_tmat(const double *__restrict__ G,
                     for (int r = 0; r < 4; ++r) acc[q][r] = 0.0;
                 // step 0: B C^{-1} (C^{-1} at rows/cols i0+s..); step 1: A^{-1} X (X in B's place)
                 const int ka = step == 0 ? i0 + s : i0;
-                for (int c = 0; c < s; ++c) {
+#pragma unroll 4
+                for (int c = 0; c < s; ++c) {  // s is a multiple of 16
                     double av[4], bv[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
