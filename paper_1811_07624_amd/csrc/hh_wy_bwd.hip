@@ -43,7 +43,7 @@ struct RankArgs {
     const void *C[2];   // coefficients for G and for X (m x ldc, 16-bit, row-major in j)
     int64_t ldc;
     float *out;         // [KS][npad][m]
-    float *gx;          // nullable: [KS][2][npad]
+    float *gx;          // nullable: [KS][4][npad]
     int n, npad;
     int64_t N, chunk;
 };
@@ -58,7 +58,10 @@ __global__ __launch_bounds__(64 * NW) void k_wy_rank(RankArgs a) {
     constexpr int T = 64 * NW;    // threads
     constexpr int RB = 32 * NW;   // rows per block
     constexpr int M = 16 * MB;
-    constexpr int RS = RB + 4;    // LDS row stride of a staged vector slice (elements)
+    // LDS row stride of a staged vector slice (elements): 16-byte aligned and
+    // 8 banks apart, so the 16 vector slices a transpose read touches spread
+    // over the banks
+    constexpr int RS = RB + 16;
     constexpr int CSd = 32 + 8;   // LDS row stride of a staged coefficient row
     constexpr int CD = 4;         // 16-byte data chunks per thread per step (8 RB of them)
     constexpr int CC = (2 * M * 4 + T - 1) / T;
@@ -81,7 +84,7 @@ __global__ __launch_bounds__(64 * NW) void k_wy_rank(RankArgs a) {
     for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) acc[r][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float gxa = 0.f;
+    float gxr[2] = {0.f, 0.f};  // sum_j G X over this lane's 8 vectors, rows 16 rbk + c
 
     v8 rd[CD], rc[CC];
     auto load_step = [&](int64_t j0) {
@@ -117,12 +120,7 @@ __global__ __launch_bounds__(64 * NW) void k_wy_rank(RankArgs a) {
         for (int t = 0; t < CD; ++t) {
             const int ci = tid + T * t;
             const int src = ci / (4 * RB), cc = ci % (4 * RB), j = cc / (RB / 8), rcn = cc % (RB / 8);
-            typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
-            const u64x2 b = __builtin_bit_cast(u64x2, rd[t]);
-            unsigned long long *dst =
-                reinterpret_cast<unsigned long long *>(sD + (src * 32 + j) * RS + 8 * rcn);
-            dst[0] = b[0];
-            dst[1] = b[1];
+            *reinterpret_cast<v8 *>(sD + (src * 32 + j) * RS + 8 * rcn) = rd[t];
         }
 #pragma unroll
         for (int t = 0; t < CC; ++t) {
@@ -140,26 +138,40 @@ __global__ __launch_bounds__(64 * NW) void k_wy_rank(RankArgs a) {
         store_step();
         __syncthreads();
         if (j0 + 32 < je) load_step(j0 + 32);
+        // B operand (K = 8 consecutive vectors, N = one row) straight from the
+        // vector-major staging by two transpose reads: within each 16-lane
+        // group, lane i receives element i % 4 of the 4-element rows addressed
+        // by lanes i/4 + 4j, so lane L of group g points at rows 4 (L % 4) ..
+        // +3 of vector 8g + L/4 (+4 for the second read), and lane (c, g) gets
+        // D[vector 8g + j][row c], j < 8.
+        v8 bfr[2][2];
+#pragma unroll
+        for (int src = 0; src < 2; ++src)
+#pragma unroll
+            for (int rbk = 0; rbk < 2; ++rbk) {
+                const int L = lane & 15;
+                const el *p0 = sD + (src * 32 + 8 * g + (L >> 2)) * RS + 32 * w + 16 * rbk + 4 * (L & 3);
+                typedef short v4s __attribute__((ext_vector_type(4)));
+                typedef __attribute__((address_space(3))) v4s *lds_v4s;
+                const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s)(p0));
+                const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s)(p0 + 4 * RS));
+                bfr[src][rbk] = __builtin_bit_cast(v8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+            }
 #pragma unroll
         for (int src = 0; src < 2; ++src) {
-            v8 bfr[2];
-#pragma unroll
-            for (int rbk = 0; rbk < 2; ++rbk)
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    bfr[rbk][q] = sD[(src * 32 + 8 * g + q) * RS + 32 * w + 16 * rbk + c];
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
                 const v8 afr = *reinterpret_cast<const v8 *>(sC + (src * M + 16 * mb + c) * CSd + 8 * g);
 #pragma unroll
-                for (int rbk = 0; rbk < 2; ++rbk) acc[rbk][mb] = E::mfma(afr, bfr[rbk], acc[rbk][mb]);
+                for (int rbk = 0; rbk < 2; ++rbk) acc[rbk][mb] = E::mfma(afr, bfr[src][rbk], acc[rbk][mb]);
             }
         }
         if (a.gx) {
-            const int row = tid % RB, half = tid / RB;
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
-                gxa += (float)sD[(16 * half + j) * RS + row] * (float)sD[(32 + 16 * half + j) * RS + row];
+            for (int rbk = 0; rbk < 2; ++rbk)
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    gxr[rbk] = __builtin_fmaf((float)bfr[0][rbk][j], (float)bfr[1][rbk][j], gxr[rbk]);
         }
     }
 #pragma unroll
@@ -170,7 +182,11 @@ __global__ __launch_bounds__(64 * NW) void k_wy_rank(RankArgs a) {
             *reinterpret_cast<f32x4 *>(a.out + ((size_t)blockIdx.y * a.npad + r) * M + 16 * mb + 4 * g) =
                 acc[rbk][mb];
     }
-    if (a.gx) a.gx[((size_t)blockIdx.y * 2 + tid / RB) * a.npad + rb0 + tid % RB] = gxa;
+    if (a.gx) {  // partials per vector group g: [KS][4][npad]
+#pragma unroll
+        for (int rbk = 0; rbk < 2; ++rbk)
+            a.gx[((size_t)blockIdx.y * 4 + g) * a.npad + rb0 + 32 * w + 16 * rbk + c] = gxr[rbk];
+    }
 }
 
 struct GramArgs {
@@ -393,7 +409,7 @@ BwdLayout bwd_layout(hh_op op, const WyShape &s, int64_t n, int64_t N) {
     L.cg = off;    off += align256((size_t)L.m * L.ldc * 2);
     L.cx = off;    off += align256((size_t)L.m * L.ldc * 2);
     L.part = off;  off += align256((size_t)L.ks * s.npad * L.m * 4);
-    L.gx = off;    off += sym ? align256((size_t)L.ks * 2 * s.npad * 4) : 0;
+    L.gx = off;    off += sym ? align256((size_t)L.ks * 4 * s.npad * 4) : 0;
     L.psum = off;  off += align256((size_t)s.npad * L.m * 8);
     L.gxsum = off; off += sym ? align256((size_t)s.npad * 8) : 0;
     L.gpart = off; off += align256((size_t)L.npairs * L.ksg * hp * hp * 4);
@@ -425,7 +441,7 @@ hipError_t launch_products(const WyShape &s, const BwdLayout &L, char *ws, const
     ra.N = N;
     ra.chunk = L.chunk;
     const dim3 rgrid(s.npad / kRankRows, L.ks);
-    const size_t rlds = (size_t)(2 * 32 * (kRankRows + 4) + 2 * L.m * (32 + 8)) * 2;
+    const size_t rlds = (size_t)(2 * 32 * (kRankRows + 16) + 2 * L.m * (32 + 8)) * 2;
     const dim3 rblock(2 * kRankRows);
     switch (L.m) {
     case 64: hipLaunchKernelGGL((k_wy_rank<E, 4, kRankRows / 32>), rgrid, rblock, rlds, st, ra); break;
@@ -566,7 +582,7 @@ hh_status wy_backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, co
                            reinterpret_cast<double *>(base + L.psum));
         if (sym)
             hipLaunchKernelGGL((k_sum_parts<float>), dim3(s.npad / 32, 1), dim3(256), 0, st,
-                               reinterpret_cast<const float *>(base + L.gx), 2 * L.ks, (size_t)s.npad,
+                               reinterpret_cast<const float *>(base + L.gx), 4 * L.ks, (size_t)s.npad,
                                s.npad, reinterpret_cast<double *>(base + L.gxsum));
     }
     CombineArgs ca{};
