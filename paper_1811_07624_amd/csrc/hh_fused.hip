@@ -6,7 +6,7 @@
 // (8h+1)n for the symmetric form).  The vector never leaves the registers
 // between its single HBM read and its single HBM write.
 //
-// Mapping: a group of LPV lanes (16, 32 or 64) owns VPL vectors; lane c holds
+// Mapping: a group of LPV lanes (16 or 64) owns VPL vectors; lane c holds
 // NC 16-byte chunks of each at element offsets i*LPV*W + c*W (W = 4 floats or
 // 2 doubles), so every load and store instruction moves LPV*16 contiguous
 // bytes per vector.  A dot product is a per-lane partial sum followed by a
@@ -15,6 +15,7 @@
 // of hc reflectors that every wave of the block walks through in lockstep;
 // each chunk of a reflector read from LDS serves the VPL vectors of the group.
 #include <algorithm>
+#include <type_traits>
 
 #include "hh_internal.h"
 
@@ -24,9 +25,7 @@ namespace {
 constexpr size_t kLdsBudget = 64 * 1024;       // several blocks per compute unit
 constexpr size_t kLdsBudgetWide = 144 * 1024;  // one 8-wave block per compute unit
 
-// PF = 1: the next vectors of the grid-stride loop are loaded while the
-// current ones are reflected (two register tiles; not for MAHAL).
-template <typename T, int LPV, int NC, int OP, int VPL, int WPB, int PF>
+template <typename T, int LPV, int NC, int OP, int VPL, int WPB>
 __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
     using VT = typename V16<T>::type;
     constexpr int W = V16<T>::W;
@@ -164,37 +163,17 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
     const int64_t vpb = (int64_t)WPB * VPW * VPL;
     const int64_t gstride = (int64_t)gridDim.x * vpb;
     const int64_t joff = (int64_t)(wave * VPW + row) * VPL;
-    [[maybe_unused]] T xn[PF ? VPL : 1][PF ? E : 1];
-    if constexpr (PF) {
-        const int64_t j0 = (int64_t)blockIdx.x * vpb + joff;
-#pragma unroll
-        for (int v = 0; v < VPL; ++v) load_vec(xn[v], static_cast<const T *>(a.X), a.ldx, j0 + v, j0 + v < a.N);
-    }
     for (int64_t b0 = (int64_t)blockIdx.x * vpb; b0 < a.N; b0 += gstride) {
         const int64_t j0 = b0 + joff;
         T x[VPL][E];
-        if constexpr (PF) {
 #pragma unroll
-            for (int v = 0; v < VPL; ++v)
-#pragma unroll
-                for (int e = 0; e < E; ++e) x[v][e] = xn[v][e];
-            const int64_t jn = j0 + gstride;
-            if (b0 + gstride < a.N) {
-#pragma unroll
-                for (int v = 0; v < VPL; ++v) load_vec(xn[v], static_cast<const T *>(a.X), a.ldx, jn + v, jn + v < a.N);
-            }
-        } else {
-#pragma unroll
-            for (int v = 0; v < VPL; ++v) load_vec(x[v], static_cast<const T *>(a.X), a.ldx, j0 + v, j0 + v < a.N);
-        }
+        for (int v = 0; v < VPL; ++v) load_vec(x[v], static_cast<const T *>(a.X), a.ldx, j0 + v, j0 + v < a.N);
         if constexpr (OP == F_MAHAL && VPL == 1) {
-            static_assert(!PF, "no prefetch for the two-input form");
             T xb[E];
             load_vec(xb, static_cast<const T *>(a.Xb), a.ldb, j0, j0 < a.N);
 #pragma unroll
             for (int e = 0; e < E; ++e) x[0][e] -= xb[e];
         } else if constexpr (OP == F_MAHAL) {
-            static_assert(!PF, "no prefetch for the two-input form");
             // x - xb one 16-byte chunk at a time (keeps the second input's
             // registers to one chunk when a lane holds two vectors)
             const T *Xb = static_cast<const T *>(a.Xb);
@@ -252,26 +231,22 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
     }
 }
 
-#ifndef HH_FUSED_PF
-#define HH_FUSED_PF 0
-#endif
-
-template <typename T, int LPV, int NC, int VPL = 1, int WPB = 4, int PF = 0>
+template <typename T, int LPV, int NC, int VPL = 1, int WPB = 4>
 hipError_t launch_op(FusedOp op, const FusedPlan &p, const FusedFwdArgs &a, dim3 grid,
                      hipStream_t st) {
     const dim3 block(WPB * kWave);
     switch (op) {
     case F_APPLY:
-        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_APPLY, VPL, WPB, PF>), grid, block, p.lds_bytes, st, a);
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_APPLY, VPL, WPB>), grid, block, p.lds_bytes, st, a);
         break;
     case F_APPLY_T:
-        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_APPLY_T, VPL, WPB, PF>), grid, block, p.lds_bytes, st, a);
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_APPLY_T, VPL, WPB>), grid, block, p.lds_bytes, st, a);
         break;
     case F_SYM:
-        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_SYM, VPL, WPB, PF>), grid, block, p.lds_bytes, st, a);
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_SYM, VPL, WPB>), grid, block, p.lds_bytes, st, a);
         break;
     case F_MAHAL:
-        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_MAHAL, VPL, WPB, 0>), grid, block, p.lds_bytes, st, a);
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_MAHAL, VPL, WPB>), grid, block, p.lds_bytes, st, a);
         break;
     }
     return hipGetLastError();
@@ -287,10 +262,11 @@ hipError_t dispatch(FusedOp op, const FusedPlan &p, const FusedFwdArgs &a, dim3 
         case 2: return launch_op<T, 16, 2>(op, p, a, grid, st);
         case 4: return launch_op<T, 16, 4>(op, p, a, grid, st);
         case 8: return launch_op<T, 16, 8>(op, p, a, grid, st);
-        case 16: return launch_op<T, 16, 16>(op, p, a, grid, st);
+        case 16:
+            if constexpr (std::is_same_v<T, float>)
+                if (p.s.vpl == 2) return launch_op<T, 16, 16, 2, 4>(op, p, a, grid, st);
+            return launch_op<T, 16, 16>(op, p, a, grid, st);
         }
-    } else if (lpv == 32) {
-        if (nc == 8 && p.s.vpl == 2 && p.s.wpb == 8) return launch_op<T, 32, 8, 2, 8, HH_FUSED_PF>(op, p, a, grid, st);
     } else if (lpv == 64) {
         switch (nc) {
         case 8: return launch_op<T, 64, 8, 2, 8>(op, p, a, grid, st);
@@ -313,14 +289,15 @@ bool fused_shape(hh_dtype t, int64_t n, FusedShape *s) {
     const int W = (t == HH_F64) ? 2 : 4;
     s->vpl = 1;
     s->wpb = 4;
-    if (t == HH_F32 && n > 16 * W * 8 && n <= 32 * W * 8) {
-        // 512 < n <= 1024: 32 lanes hold two vectors each, so each reflector
-        // chunk read from LDS serves two vectors; 8 waves per block keep four
-        // waves per SIMD resident within the LDS of one compute unit
-        s->lpv = 32;
-        s->nc = 8;
+    if (t == HH_F32 && n > 16 * W * 8 && n <= 16 * W * 16) {
+        // 512 < n <= 1024: each 16-lane row holds two vectors, so each
+        // reflector chunk read from LDS serves two vectors and a dot product
+        // needs only the four DPP steps of one row (this size is bound by
+        // VALU issue, and the 32-lane layout spent a further four
+        // instructions per reduction)
+        s->lpv = 16;
+        s->nc = 16;
         s->vpl = 2;
-        s->wpb = 8;
     } else if (n <= 16 * W * 16) {
         s->lpv = 16;
         s->nc = next_pow2((n + 16 * W - 1) / (16 * W));
@@ -362,12 +339,8 @@ hipError_t launch_fused_fwd(const FusedPlan &p, FusedOp op, const FusedFwdArgs &
                             hipStream_t st) {
     const int vpb = p.s.wpb * (kWave / p.s.lpv) * p.s.vpl;
     const int64_t need = (p.N + vpb - 1) / vpb;
-#ifndef HH_FUSED_GRIDMUL_PF
-#define HH_FUSED_GRIDMUL_PF 8
-#endif
-    // blocks per compute unit in the grid (the prefetching form keeps one
-    // block per compute unit resident and walks the batch in long strides)
-    const int64_t cap = (int64_t)device_cu_count() * (p.s.vpl > 1 ? HH_FUSED_GRIDMUL_PF : 8);
+    // a grid-stride loop over at most 8 blocks per compute unit
+    const int64_t cap = (int64_t)device_cu_count() * 8;
     const dim3 grid((unsigned)std::max<int64_t>(1, std::min(need, cap)));
     if (p.t == HH_F32) return dispatch<float>(op, p, a, grid, st);
     return dispatch<double>(op, p, a, grid, st);

@@ -82,15 +82,8 @@ __device__ __forceinline__ double read_lane(double v, int l) {
 
 // Sum over the LPV lanes that share one vector; every one of them gets it.
 template <int LPV, typename T> __device__ __forceinline__ T group_sum(T v) {
-    static_assert(LPV == 16 || LPV == 32 || LPV == 64, "16, 32 or 64 lanes per vector");
+    static_assert(LPV == 16 || LPV == 64, "16 or 64 lanes per vector");
     v = row_sum16(v);
-    if constexpr (LPV == 32) {
-        // rows 1 and 3 add lane 15 of rows 0 and 2; lanes 31 and 63 then
-        // hold the sums of the two 32-lane groups
-        v += dpp_mov<0x142, 0xA>(v);
-        const T s0 = read_lane(v, 31), s1 = read_lane(v, 63);
-        v = (__lane_id() < 32) ? s0 : s1;
-    }
     if constexpr (LPV == 64) {
         v += dpp_mov<0x142, 0xA>(v);
         v += dpp_mov<0x143, 0xC>(v);
@@ -125,7 +118,7 @@ __global__ __launch_bounds__(256) void k_sum_parts(const T *__restrict__ part, i
 
 // ---------------------------------------------------------------------------
 // Kernel selection for the fused (sequential-reflector) kernels: LPV lanes
-// own one vector, each lane NC 16-byte chunks of it; npad = NC*LPV*W >= n.
+// (16 or 64) own one vector, each lane NC 16-byte chunks of it; npad = NC*LPV*W >= n.
 // The forward kernel may hold VPL vectors per lane group (each reflector
 // chunk read from LDS then serves VPL vectors) and run WPB waves per block.
 struct FusedShape {
