@@ -102,12 +102,15 @@ __global__ __launch_bounds__(256) void k_wy_norm(const float *__restrict__ U, in
 // 16-bit values is exact): Gp[s][a][b] = sum over the rows of segment s of
 // y_a y_b, for the 16 x 16 tiles (ta, tb), ta <= tb, one block per (tile
 // pair, segment).  Each step stages the fragments (ta, q) and (tb, q) of the
-// fragment-ordered copy (32 rows each) in LDS.
+// fragment-ordered copy (32 rows each) in LDS.  With lam, the same pass also
+// forms Mp[s][a][b] = sum of y_a lam_r y_b (exact in FP64 too: 11 + 11 + 24
+// significant bits), the matrix Y^T diag(lam) Y of the symmetric form.
 template <typename E>
 __global__ __launch_bounds__(256) void k_wy_gram(const typename E::elem *__restrict__ Yc, int npad,
-                                                int hp, double *__restrict__ Gp) {
+                                                int hp, const float *__restrict__ lam,
+                                                double *__restrict__ Gp, double *__restrict__ Mp) {
     using v8 = typename E::vec8;
-    __shared__ double ya[32][17], yb[32][17];
+    __shared__ double ya[32][17], yb[32][17], lr[32];
     const int nhb = hp >> 4;
     int pr = blockIdx.x, ta = 0;
     while (pr >= nhb - ta) {
@@ -117,7 +120,7 @@ __global__ __launch_bounds__(256) void k_wy_gram(const typename E::elem *__restr
     const int tb = ta + pr;
     const int nq = npad >> 5, qs = nq / kGramSeg, seg = blockIdx.y;
     const int t = threadIdx.x, i = t >> 4, j = t & 15;
-    double acc = 0.0;
+    double acc = 0.0, accm = 0.0;
     for (int q = seg * qs; q < (seg + 1) * qs; ++q) {
         __syncthreads();
         if (t < 128) {
@@ -127,12 +130,25 @@ __global__ __launch_bounds__(256) void k_wy_gram(const typename E::elem *__restr
             double(*dst)[17] = which ? yb : ya;
 #pragma unroll
             for (int e = 0; e < 8; ++e) dst[8 * (ln >> 4) + e][ln & 15] = (double)v[e];
+        } else if (lam && t < 160) {
+            lr[t - 128] = (double)lam[32 * q + t - 128];
         }
         __syncthreads();
+        if (lam) {
 #pragma unroll 8
-        for (int r = 0; r < 32; ++r) acc += ya[r][i] * yb[r][j];
+            for (int r = 0; r < 32; ++r) {
+                const double p = ya[r][i] * yb[r][j];
+                acc += p;
+                accm += p * lr[r];
+            }
+        } else {
+#pragma unroll 8
+            for (int r = 0; r < 32; ++r) acc += ya[r][i] * yb[r][j];
+        }
     }
-    Gp[((size_t)seg * hp + 16 * ta + i) * hp + 16 * tb + j] = acc;
+    const size_t o = ((size_t)seg * hp + 16 * ta + i) * hp + 16 * tb + j;
+    Gp[o] = acc;
+    if (lam) Mp[o] = accm;
 }
 
 // T = (diag(||y_k||^2/2) + striu(G))^{-1}, upper triangular, FP64, by blocked
@@ -242,6 +258,30 @@ __global__ __launch_bounds__(256) void k_wy_tfrag(const double *__restrict__ Tw,
         const double t = tr ? Tw[col * hp + r] : Tw[r * hp + col];
         const el hi = (el)t;
         Tf[(size_t)id * 8 + j] = hl ? (el)(t - (double)hi) : hi;
+    }
+}
+
+// Y^T diag(lam) Y (symmetric; the Gram pass fills only the tiles ta <= tb)
+// as 16-bit MFMA A-operand fragments split into hi + lo parts, laid out as
+// the tr = 0 half of k_wy_tfrag's output: fragment (hl, ib, kb), lane (c, g),
+// element j holds M[sigma_row(ib, c)][32 kb + 8 g + j].
+template <typename E>
+__global__ __launch_bounds__(256) void k_wy_mfrag(const double *__restrict__ Ms, int hp,
+                                                 typename E::elem *__restrict__ Mf) {
+    using el = typename E::elem;
+    const int HB = hp >> 4, KS = hp >> 5;
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= 2 * HB * KS * 64) return;
+    const int lane = id & 63, f = id >> 6;
+    const int kb = f % KS, ib = (f / KS) % HB, hl = f / (KS * HB);
+    const int c = lane & 15, g = lane >> 4;
+    const int r = sigma_row(ib, c);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int col = 32 * kb + 8 * g + j;
+        const double m = (r >> 4) <= (col >> 4) ? Ms[r * hp + col] : Ms[col * hp + r];
+        const el hi = (el)m;
+        Mf[(size_t)id * 8 + j] = hl ? (el)(m - (double)hi) : hi;
     }
 }
 
@@ -527,10 +567,15 @@ __global__ void k_fill_lam(const float *__restrict__ lam, int n, int npad, float
 }
 
 template <typename E>
-hipError_t wy_setup(const WyShape &s, const float *U, int64_t ldu, int64_t n, int64_t h, char *ws,
-                    const WyWs &w, bool want_uh, hipStream_t st) {
+hipError_t wy_setup(const WyShape &s, const float *U, int64_t ldu, int64_t n, int64_t h,
+                    const float *lam, bool want_m, char *ws, const WyWs &w, bool want_uh,
+                    hipStream_t st) {
     using el = typename E::elem;
     const int hp = s.hp;
+    const bool m = lam && want_m;
+    if (lam)
+        hipLaunchKernelGGL(k_fill_lam, dim3((s.npad + 255) / 256), dim3(256), 0, st, lam, (int)n, s.npad,
+                           reinterpret_cast<float *>(ws + w.lam));
     hipLaunchKernelGGL((k_wy_norm<E>), dim3(hp), dim3(256), 0, st, U, ldu, (int)n, (int)h, s.npad,
                        hp, reinterpret_cast<el *>(ws + w.yc), reinterpret_cast<el *>(ws + w.yr),
                        reinterpret_cast<el *>(ws + w.ycs),
@@ -538,12 +583,14 @@ hipError_t wy_setup(const WyShape &s, const float *U, int64_t ldu, int64_t n, in
                        reinterpret_cast<double *>(ws + w.nrmraw),
                        want_uh ? reinterpret_cast<double *>(ws + w.uh64) : nullptr);
     const int nhb = hp / 16;
+    const size_t hh = (size_t)hp * hp;
+    double *gp = reinterpret_cast<double *>(ws + w.gram);
     hipLaunchKernelGGL((k_wy_gram<E>), dim3(nhb * (nhb + 1) / 2, kGramSeg), dim3(256), 0, st,
                        reinterpret_cast<const el *>(ws + w.yc), s.npad, hp,
-                       reinterpret_cast<double *>(ws + w.gram));
-    hipLaunchKernelGGL((k_sum_parts<double>), dim3(hp * hp / 32, 1), dim3(256), 0, st,
-                       reinterpret_cast<const double *>(ws + w.gram), kGramSeg, (size_t)hp * hp, hp * hp,
-                       reinterpret_cast<double *>(ws + w.gsum));
+                       m ? reinterpret_cast<const float *>(ws + w.lam) : nullptr, gp,
+                       m ? gp + kGramSeg * hh : nullptr);
+    hipLaunchKernelGGL((k_sum_parts<double>), dim3(hp * hp / 32, m ? 2 : 1), dim3(256), 0, st, gp, kGramSeg,
+                       hh, hp * hp, reinterpret_cast<double *>(ws + w.gsum));
     hipLaunchKernelGGL(k_wy_tmat, dim3(1), dim3(256), (size_t)hp * (hp + 1) * 8, st,
                        reinterpret_cast<const double *>(ws + w.gsum),
                        reinterpret_cast<const double *>(ws + w.nrm2), hp,
@@ -551,6 +598,10 @@ hipError_t wy_setup(const WyShape &s, const float *U, int64_t ldu, int64_t n, in
     const int nfrag = 4 * (hp / 16) * (hp / 32) * 64;
     hipLaunchKernelGGL((k_wy_tfrag<E>), dim3((nfrag + 255) / 256), dim3(256), 0, st,
                        reinterpret_cast<const double *>(ws + w.tw), hp, reinterpret_cast<el *>(ws + w.tf));
+    if (m)
+        hipLaunchKernelGGL((k_wy_mfrag<E>), dim3((nfrag / 2 + 255) / 256), dim3(256), 0, st,
+                           reinterpret_cast<const double *>(ws + w.gsum) + hh, hp,
+                           reinterpret_cast<el *>(ws + w.mf));
     return hipGetLastError();
 }
 
@@ -590,14 +641,10 @@ hipError_t dispatch_main(const WyShape &s, WyOp op, const WyArgs &a, hipStream_t
 }  // namespace
 
 hipError_t wy_setup_any(bool bf, const WyShape &s, const float *U, int64_t ldu, int64_t n,
-                        int64_t h, char *ws, const WyWs &w, bool want_uh, hipStream_t st) {
-    return bf ? wy_setup<BF16>(s, U, ldu, n, h, ws, w, want_uh, st)
-              : wy_setup<F16>(s, U, ldu, n, h, ws, w, want_uh, st);
-}
-
-hipError_t wy_fill_lam(const float *lam, int n, int npad, float *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_fill_lam, dim3((npad + 255) / 256), dim3(256), 0, st, lam, n, npad, out);
-    return hipGetLastError();
+                        int64_t h, const float *lam, bool want_m, char *ws, const WyWs &w,
+                        bool want_uh, hipStream_t st) {
+    return bf ? wy_setup<BF16>(s, U, ldu, n, h, lam, want_m, ws, w, want_uh, st)
+              : wy_setup<F16>(s, U, ldu, n, h, lam, want_m, ws, w, want_uh, st);
 }
 
 // Which main kernel runs: 0 = register-resident tile, 1 = streaming, 2 = by shape.
@@ -613,7 +660,7 @@ hipError_t wy_fill_lam(const float *lam, int n, int npad, float *out, hipStream_
 // 2^18 vectors; at n hp = 2^20 (n = 8192, h = 128) Q diag(lam) Q^T X takes
 // 1.66 ms vs 1.35 ms for 2^16 vectors.  A pass that only emits the
 // backward's coefficients reads X once in either kernel, and streams faster.
-static bool use_stream(const WyShape &s, const WyArgs &a) {
+bool wy_stream_selected(const WyShape &s, const WyArgs &a) {
     // 32-bit buffer offsets: a tile of 256 vectors and the coefficient rows
     const int64_t lim = (int64_t)1 << 31;
     if (256 * std::max(a.ldx, a.ldy) * 2 >= lim) return false;
@@ -625,7 +672,7 @@ static bool use_stream(const WyShape &s, const WyArgs &a) {
 
 hipError_t wy_main_any(bool bf, const WyShape &s, WyOp op, const WyArgs &a, hipStream_t st) {
     if (a.N == 0) return hipSuccess;
-    if (use_stream(s, a)) return wy_stream_any(bf, s, op, a, st);
+    if (wy_stream_selected(s, a)) return wy_stream_any(bf, s, op, a, st);
     return bf ? dispatch_main<BF16>(s, op, a, st) : dispatch_main<F16>(s, op, a, st);
 }
 
@@ -670,14 +717,6 @@ hh_status wy_forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, con
         return set_error(HH_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", w.total, ws_bytes);
     char *base = static_cast<char *>(ws);
     const bool bf = d->compute_dtype == HH_BF16;
-    hipError_t e = bf ? wy_setup<BF16>(s, static_cast<const float *>(U), ldu, n, h, base, w, false, st)
-                      : wy_setup<F16>(s, static_cast<const float *>(U), ldu, n, h, base, w, false, st);
-    if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY setup launch: %s", hipGetErrorString(e));
-    if (op == HH_OP_SYM) {
-        hipLaunchKernelGGL(k_fill_lam, dim3((s.npad + 255) / 256), dim3(256), 0, st,
-                           static_cast<const float *>(lam), (int)n, s.npad,
-                           reinterpret_cast<float *>(base + w.lam));
-    }
     WyArgs a{};
     a.X = X;
     a.ldx = ldx;
@@ -687,12 +726,18 @@ hh_status wy_forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, con
     a.Yr = base + w.yr;
     a.Ycs = base + w.ycs;
     a.Tf = base + w.tf;
+    a.Mf = base + w.mf;
     a.Tm = reinterpret_cast<const float *>(base + w.tm);
     a.lam = reinterpret_cast<const float *>(base + w.lam);
     a.store = 1;
     a.n = (int)n;
     a.npad = s.npad;
     a.N = N;
+    const bool sym = op == HH_OP_SYM;
+    hipError_t e = wy_setup_any(bf, s, static_cast<const float *>(U), ldu, n, h,
+                                sym ? static_cast<const float *>(lam) : nullptr,
+                                sym && wy_stream_selected(s, a), base, w, false, st);
+    if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY setup launch: %s", hipGetErrorString(e));
     const WyOp wop = op == HH_OP_APPLY ? W_APPLY : op == HH_OP_APPLY_T ? W_APPLY_T : W_SYM;
     e = wy_main_any(bf, s, wop, a, st);
     if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY kernel launch: %s", hipGetErrorString(e));

@@ -509,13 +509,39 @@ hh_status wy_backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, co
 
     char *base = static_cast<char *>(ws);
     const bool bf = d->compute_dtype == HH_BF16;
-    hipError_t e = wy_setup_any(bf, s, static_cast<const float *>(U), ldu, n, h, base, L.base, true, st);
+    WyArgs a{};
+    a.Yc = base + L.base.yc;
+    a.Yr = base + L.base.yr;
+    a.Ycs = base + L.base.ycs;
+    a.Tf = base + L.base.tf;
+    a.Mf = base + L.base.mf;
+    a.Tm = reinterpret_cast<const float *>(base + L.base.tm);
+    a.lam = reinterpret_cast<const float *>(base + L.base.lam);
+    a.ldc = L.ldc;
+    a.n = (int)n;
+    a.npad = s.npad;
+    a.N = N;
+    const WyOp xop = op == HH_OP_APPLY_BWD ? W_APPLY : op == HH_OP_APPLY_T_BWD ? W_APPLY_T : W_SYM;
+    const WyOp gop = op == HH_OP_APPLY_BWD ? W_APPLY_T : op == HH_OP_APPLY_T_BWD ? W_APPLY : W_SYM;
+    WyArgs ax = a;  // pass over X: coefficients only
+    ax.X = X;
+    ax.ldx = ldx;
+    ax.Y = const_cast<void *>(X);
+    ax.ldy = ldx;
+    ax.coef = base + L.cg;
+    ax.store = 0;
+    WyArgs ag = a;  // pass over G: coefficients and dX
+    ag.X = G;
+    ag.ldx = ldg;
+    ag.Y = dX ? dX : const_cast<void *>(G);
+    ag.ldy = dX ? lddx : ldg;
+    ag.coef = want_params ? base + L.cx : nullptr;
+    ag.store = dX ? 1 : 0;
+    const bool want_m = sym && ((want_params && wy_stream_selected(s, ax)) || wy_stream_selected(s, ag));
+    hipError_t e = wy_setup_any(bf, s, static_cast<const float *>(U), ldu, n, h,
+                                sym ? static_cast<const float *>(lam) : nullptr, want_m, base, L.base,
+                                true, st);
     if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY setup launch: %s", hipGetErrorString(e));
-    if (sym) {
-        e = wy_fill_lam(static_cast<const float *>(lam), (int)n, s.npad,
-                        reinterpret_cast<float *>(base + L.base.lam), st);
-        if (e != hipSuccess) return set_error(HH_ERR_HIP, "launch: %s", hipGetErrorString(e));
-    }
     const int64_t padn = (int64_t)L.m * (L.ldc - N);
     if (padn > 0) {
         const dim3 zg((unsigned)((padn + 255) / 256));
@@ -527,41 +553,12 @@ hh_status wy_backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, co
             hipLaunchKernelGGL((k_zero_cols<_Float16>), zg, dim3(256), 0, st, reinterpret_cast<_Float16 *>(base + L.cx), L.m, N, L.ldc);
         }
     }
-    WyArgs a{};
-    a.Yc = base + L.base.yc;
-    a.Yr = base + L.base.yr;
-    a.Ycs = base + L.base.ycs;
-    a.Tf = base + L.base.tf;
-    a.Tm = reinterpret_cast<const float *>(base + L.base.tm);
-    a.lam = reinterpret_cast<const float *>(base + L.base.lam);
-    a.ldc = L.ldc;
-    a.n = (int)n;
-    a.npad = s.npad;
-    a.N = N;
-    const WyOp xop = op == HH_OP_APPLY_BWD ? W_APPLY : op == HH_OP_APPLY_T_BWD ? W_APPLY_T : W_SYM;
-    const WyOp gop = op == HH_OP_APPLY_BWD ? W_APPLY_T : op == HH_OP_APPLY_T_BWD ? W_APPLY : W_SYM;
-    if (want_params) {  // pass over X: coefficients only
-        WyArgs ax = a;
-        ax.X = X;
-        ax.ldx = ldx;
-        ax.Y = const_cast<void *>(X);
-        ax.ldy = ldx;
-        ax.coef = base + L.cg;
-        ax.store = 0;
+    if (want_params) {
         e = wy_main_any(bf, s, xop, ax, st);
         if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY pass over X: %s", hipGetErrorString(e));
     }
-    {  // pass over G: coefficients and dX
-        WyArgs ag = a;
-        ag.X = G;
-        ag.ldx = ldg;
-        ag.Y = dX ? dX : const_cast<void *>(G);
-        ag.ldy = dX ? lddx : ldg;
-        ag.coef = want_params ? base + L.cx : nullptr;
-        ag.store = dX ? 1 : 0;
-        e = wy_main_any(bf, s, gop, ag, st);
-        if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY pass over dY: %s", hipGetErrorString(e));
-    }
+    e = wy_main_any(bf, s, gop, ag, st);
+    if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY pass over dY: %s", hipGetErrorString(e));
     if (!want_params) return HH_OK;
     e = bf ? launch_products<BF16>(s, L, base, G, ldg, X, ldx, N, (int)n, sym, st)
            : launch_products<F16>(s, L, base, G, ldg, X, ldx, N, (int)n, sym, st);

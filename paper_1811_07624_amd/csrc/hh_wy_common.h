@@ -93,6 +93,7 @@ struct WyArgs {
     const void *Yr;   // npad x HP, row-major reflectors (GEMM2 A operand)
     const void *Ycs;  // streaming kernel: GEMM1 operand, chunk-major (ycs_index)
     const void *Tf;   // streaming kernel: T and T^T as 16-bit hi/lo MFMA fragments
+    const void *Mf;   // streaming kernel, SYM: Y^T diag(lam) Y as hi/lo fragments
     const float *Tm;  // HP x HP row-major
     const float *lam; // npad (SYM)
     void *coef;       // nullable: W' of pass q written to rows [q*HP, (q+1)*HP), ld = ldc
@@ -121,8 +122,12 @@ inline bool wy_shape(int64_t n, int64_t h, WyShape *s) {
 constexpr int kGramSeg = 16;
 
 // Workspace of the WY setup (shared by forward and backward).
+// Workspace of the WY path.  With lam (Q diag(lam) Q^T X) the Gram buffers
+// hold a second matrix after the first: gram -> [2][kGramSeg][hp][hp]
+// partials, gsum -> [2][hp][hp] (Y^T Y, then Y^T diag(lam) Y), and mf holds
+// the fragments of the second.
 struct WyWs {
-    size_t yc, yr, ycs, tf, nrm2, nrmraw, gram, gsum, tw, tm, lam, uh64, total;
+    size_t yc, yr, ycs, tf, mf, nrm2, nrmraw, gram, gsum, tw, tm, lam, uh64, total;
 };
 
 inline WyWs wy_ws(const WyShape &s, int64_t n, bool with_lam, bool bwd) {
@@ -132,11 +137,13 @@ inline WyWs wy_ws(const WyShape &s, int64_t n, bool with_lam, bool bwd) {
     w.yc = off;     off += align256(hp * np * 2);
     w.yr = off;     off += align256(hp * np * 2);
     w.ycs = off;    off += align256(hp * np * 2);
+    const size_t nm = with_lam ? 2 : 1;
     w.tf = off;     off += align256(4 * hp * hp * 2);
+    w.mf = off;     off += with_lam ? align256(2 * hp * hp * 2) : 0;
     w.nrm2 = off;   off += align256(hp * 8);
     w.nrmraw = off; off += align256(hp * 8);
-    w.gram = off;   off += align256(kGramSeg * hp * hp * 8);
-    w.gsum = off;   off += align256(hp * hp * 8);
+    w.gram = off;   off += align256(nm * kGramSeg * hp * hp * 8);
+    w.gsum = off;   off += align256(nm * hp * hp * 8);
     w.tw = off;     off += align256(hp * hp * 8);
     w.tm = off;     off += align256(hp * hp * 4);
     w.lam = off;    off += with_lam ? align256(np * 4) : 0;
@@ -146,9 +153,13 @@ inline WyWs wy_ws(const WyShape &s, int64_t n, bool with_lam, bool bwd) {
 }
 
 // Launchers defined in hh_wy.hip.
+// Setup: normalised reflectors, T; with lam also the padded spectrum and,
+// when want_m, the fragments of Y^T diag(lam) Y (streaming symmetric form).
 hipError_t wy_setup_any(bool bf, const WyShape &s, const float *U, int64_t ldu, int64_t n,
-                        int64_t h, char *ws, const WyWs &w, bool want_uh, hipStream_t st);
-hipError_t wy_fill_lam(const float *lam, int n, int npad, float *out, hipStream_t st);
+                        int64_t h, const float *lam, bool want_m, char *ws, const WyWs &w,
+                        bool want_uh, hipStream_t st);
+// True when wy_main_any runs the streaming kernel for these arguments.
+bool wy_stream_selected(const WyShape &s, const WyArgs &a);
 hipError_t wy_main_any(bool bf, const WyShape &s, WyOp op, const WyArgs &a, hipStream_t st);
 
 // Defined in hh_wy_stream.hip.

@@ -10,10 +10,13 @@
 //   phase 1   W = Y^T X                       (GEMM1, reduction over the rows)
 //   T step    Z = T W  (Q X)  or  T^T W  (Q^T X)
 //   phase 3   Y_out = X - Y Z                 (GEMM2)
-// and for Q diag(lam) Q^T X:
-//   phase 1   W1 = Y^T X,  Z1 = T^T W1
-//   phase 2   s = lam .* (X - Y Z1) rounded to 16 bits,  W2 = Y^T s,  Z2 = T W2
-//   phase 3   Y_out = s - Y Z2, with s recomputed from X exactly as in phase 2.
+// and for Q diag(lam) Q^T X, with s = lam .* (X - Y Z1) = diag(lam) Q^T X:
+//   phase 1   W1 = Y^T X,  V = Y^T (lam .* X)  (both from one read of X)
+//   T steps   Z1 = T^T W1,  W2 = V - M Z1 (= Y^T s, M = Y^T diag(lam) Y),
+//             Z2 = T W2
+//   phase 3   Y_out = s - Y Z2, s formed from X and rounded to 16 bits.
+// Forming Y^T s from V and M instead of from s itself saves a full read of X
+// (two reads and one write instead of three reads and one write).
 // Reflector chunks reach all 8 waves through LDS (two slots), fetched D chunks
 // ahead through registers together with each wave's own X chunk; loads are
 // issued reflectors first so that waiting for them never waits for the X
@@ -31,7 +34,7 @@
 //  * T and W enter the T product as 16-bit hi + lo parts (three products,
 //    lo*lo dropped), Z enters GEMM2 as hi + lo parts: the corrections keep
 //    about twice the 16-bit precision, as in the register-resident kernel
-//    (except the recomputed Y Z1 of the symmetric form, see gemm2h).
+//    (except the Y Z1 of the symmetric form's last phase, see gemm2x2).
 #include <algorithm>
 
 #include "hh_wy_common.h"
@@ -70,6 +73,7 @@ __global__ __launch_bounds__(kST, 2 * BPC) void k_wy_stream(WyArgs a) {
     const __amdgpu_buffer_rsrc_t rYr = make_rsrc(a.Yr, (uint32_t)HP * a.npad * 2);
     const __amdgpu_buffer_rsrc_t rLam = make_rsrc(a.lam, (uint32_t)a.npad * 4);
     const __amdgpu_buffer_rsrc_t rTf = make_rsrc(a.Tf, (uint32_t)(8 * HP * HP));
+    const __amdgpu_buffer_rsrc_t rMf = make_rsrc(a.Mf, OP == W_SYM ? (uint32_t)(4 * HP * HP) : 0u);
     const el *X = static_cast<const el *>(a.X);
     el *Yo = static_cast<el *>(a.Y);
     const int wcol = 16 * NCB * w;  // first vector of this wave within the tile
@@ -180,30 +184,14 @@ __global__ __launch_bounds__(kST, 2 * BPC) void k_wy_stream(WyArgs a) {
             }
         }
     };
-    // Correction Yr(qi, m) Z1 from Z1's high part only: it is the
-    // recomputation of t = x - Y Z1 in phases 2 and 3, which is scaled by lam
-    // and rounded to 16 bits at once, so Z1's low part changes s by less than
-    // that rounding (measured at n = 8192, h = 128: max relative error of
-    // Q diag(lam) Q^T X 3.33e-4 -> 3.40e-4 in FP16, 2.67e-3 -> 2.74e-3 in BF16),
-    // for a quarter fewer products in those phases.  Both phases use it, so s
-    // is identical in both.
-    auto gemm2h = [&](const unsigned char *sl, int qi, const v8(&z)[2][KS][NCB], f32x4(&o)[NCB][2]) {
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) o[cb][0] = o[cb][1] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const v8 a0 = lds_frag(sl + YCS_B + ((qi * 2 + 0) * KS + ks) * 1024);
-            const v8 a1 = lds_frag(sl + YCS_B + ((qi * 2 + 1) * KS + ks) * 1024);
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) {
-                o[cb][0] = E::mfma(a0, z[0][ks][cb], o[cb][0]);
-                o[cb][1] = E::mfma(a1, z[0][ks][cb], o[cb][1]);
-            }
-        }
-    };
     // Both corrections of the symmetric form's last phase from one read of
-    // the GEMM2 operand: o[cb][m] = Yr(qi, m) Z1 (high part, as gemm2h),
-    // o2[cb][m] = Yr(qi, m) Z2 (high and low parts).
+    // the GEMM2 operand: o[cb][m] = Yr(qi, m) Z1 from Z1's high part only, and
+    // o2[cb][m] = Yr(qi, m) Z2 (high and low parts).  The first forms
+    // t = x - Y Z1, which is scaled by lam and rounded to 16 bits at once, so
+    // Z1's low part changes s by less than that rounding (measured at
+    // n = 8192, h = 128: max relative error of Q diag(lam) Q^T X
+    // 3.33e-4 -> 3.40e-4 in FP16, 2.67e-3 -> 2.74e-3 in BF16), for a quarter
+    // fewer products.
     auto gemm2x2 = [&](const unsigned char *sl, int qi, const v8(&z)[2][KS][NCB], const v8(&z2)[2][KS][NCB],
                        f32x4(&o)[NCB][2], f32x4(&o2)[NCB][2]) {
 #pragma unroll
@@ -233,7 +221,33 @@ __global__ __launch_bounds__(kST, 2 * BPC) void k_wy_stream(WyArgs a) {
             for (int cb = 0; cb < NCB; ++cb) acc[hb][cb] = E::mfma(av, b[cb], acc[hb][cb]);
         }
     };
-    // s = lam .* (x - o), 16-bit (identical in phases 2 and 3)
+    // Both GEMM1 products of the symmetric form's phase 1 from one read of
+    // each A fragment: acc += Ycs^T b, acc2 += Ycs^T b2.
+    auto gemm1x2 = [&](const unsigned char *sl, int qi, const v8(&b)[NCB], const v8(&b2)[NCB],
+                       f32x4(&acc)[HB][NCB], f32x4(&acc2)[HB][NCB]) {
+#pragma unroll
+        for (int hb = 0; hb < HB; ++hb) {
+            const v8 av = lds_frag(sl + (qi * HB + hb) * 1024);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                acc[hb][cb] = E::mfma(av, b[cb], acc[hb][cb]);
+                acc2[hb][cb] = E::mfma(av, b2[cb], acc2[hb][cb]);
+            }
+        }
+    };
+    // lam .* x, 16-bit
+    auto lamx = [&](const unsigned char *sl, int qi, const v8 &x) {
+        const f32x4 l0 = *reinterpret_cast<const f32x4 *>(sl + YCS_B + YR_B + (qi * 32 + 8 * g) * 4);
+        const f32x4 l1 = *reinterpret_cast<const f32x4 *>(sl + YCS_B + YR_B + (qi * 32 + 8 * g + 4) * 4);
+        v8 r;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            r[j] = (el)((float)x[j] * l0[j]);
+            r[j + 4] = (el)((float)x[j + 4] * l1[j]);
+        }
+        return r;
+    };
+    // s = lam .* (x - o), 16-bit
     auto scaled = [&](const unsigned char *sl, int qi, const v8 &x, const f32x4(&o)[2]) {
         const f32x4 l0 = *reinterpret_cast<const f32x4 *>(sl + YCS_B + YR_B + (qi * 32 + 8 * g) * 4);
         const f32x4 l1 = *reinterpret_cast<const f32x4 *>(sl + YCS_B + YR_B + (qi * 32 + 8 * g + 4) * 4);
@@ -302,6 +316,34 @@ __global__ __launch_bounds__(kST, 2 * BPC) void k_wy_stream(WyArgs a) {
         }
     };
 
+    // acc -= M Z for the symmetric form (M and Z as hi + lo parts, lo*lo
+    // dropped).  Z is in the B-operand layout of GEMM2 (K = h in order) and
+    // M's rows are permuted like T's in tstep, so the product lands in
+    // GEMM1's accumulator layout.
+    auto mstep = [&](const v8(&z)[2][KS][NCB], f32x4(&acc)[HB][NCB]) {
+#pragma unroll
+        for (int ib = 0; ib < HB; ++ib) {
+            v8 mh[KS], ml[KS];
+#pragma unroll
+            for (int kb = 0; kb < KS; ++kb) {
+                mh[kb] = bload<v8>(rMf, lane * 16, ((0 * HB + ib) * KS + kb) * 1024);
+                ml[kb] = bload<v8>(rMf, lane * 16, ((1 * HB + ib) * KS + kb) * 1024);
+            }
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                f32x4 mz = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kb = 0; kb < KS; ++kb) {
+                    mz = E::mfma(mh[kb], z[0][kb][cb], mz);
+                    mz = E::mfma(mh[kb], z[1][kb][cb], mz);
+                    mz = E::mfma(ml[kb], z[0][kb][cb], mz);
+                }
+                acc[ib][cb] -= mz;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
     const int64_t ntiles = (a.N + V - 1) / V;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t col0 = tile * V;
@@ -314,36 +356,39 @@ __global__ __launch_bounds__(kST, 2 * BPC) void k_wy_stream(WyArgs a) {
             bstore<v8>(rYo, y, 32 * q + 8 * g < n ? vo_y[cb] + 64 * q : (int)0x80000000, 0);
         };
 
-        f32x4 acc[HB][NCB];
+        constexpr bool SYM = OP == W_SYM;
+        f32x4 acc[HB][NCB], acc2[SYM ? HB : 1][NCB];
 #pragma unroll
         for (int hb = 0; hb < HB; ++hb)
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) acc[hb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        sweep(Parts<true, false, false>{}, [&](int ch, const unsigned char *sl, const v8(&xc)[QC][NCB]) {
-#pragma unroll
-            for (int qi = 0; qi < QC; ++qi) gemm1(sl, qi, xc[qi], acc);
-        });
-        v8 z1[2][KS][NCB];
-        tstep(acc, OP == W_APPLY ? 0 : 1, 0, col0, z1);
-
-        if constexpr (OP == W_SYM) {
+        if constexpr (SYM) {
 #pragma unroll
             for (int hb = 0; hb < HB; ++hb)
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) acc[hb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-            sweep(Parts<true, true, true>{}, [&](int ch, const unsigned char *sl, const v8(&xc)[QC][NCB]) {
+                for (int cb = 0; cb < NCB; ++cb) acc2[hb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+            sweep(Parts<true, false, true>{}, [&](int ch, const unsigned char *sl, const v8(&xc)[QC][NCB]) {
 #pragma unroll
                 for (int qi = 0; qi < QC; ++qi) {
-                    f32x4 o[NCB][2];
-                    gemm2h(sl, qi, z1, o);
-                    v8 sv[NCB];
+                    v8 lx[NCB];
 #pragma unroll
-                    for (int cb = 0; cb < NCB; ++cb) sv[cb] = scaled(sl, qi, xc[qi][cb], o[cb]);
-                    gemm1(sl, qi, sv, acc);
+                    for (int cb = 0; cb < NCB; ++cb) lx[cb] = lamx(sl, qi, xc[qi][cb]);
+                    gemm1x2(sl, qi, xc[qi], lx, acc, acc2);
                 }
             });
+        } else {
+            sweep(Parts<true, false, false>{}, [&](int ch, const unsigned char *sl, const v8(&xc)[QC][NCB]) {
+#pragma unroll
+                for (int qi = 0; qi < QC; ++qi) gemm1(sl, qi, xc[qi], acc);
+            });
+        }
+        v8 z1[2][KS][NCB];
+        tstep(acc, OP == W_APPLY ? 0 : 1, 0, col0, z1);
+
+        if constexpr (SYM) {
+            mstep(z1, acc2);
             v8 z2[2][KS][NCB];
-            tstep(acc, 0, 1, col0, z2);
+            tstep(acc2, 0, 1, col0, z2);
             if (a.store) {
                 sweep(Parts<false, true, true>{}, [&](int ch, const unsigned char *sl, const v8(&xc)[QC][NCB]) {
 #pragma unroll
