@@ -656,9 +656,9 @@ hipError_t wy_setup_any(bool bf, const WyShape &s, const float *U, int64_t ldu, 
 // the whole reflector matrix from L2 for every 16-32 vectors; the streaming
 // kernel amortises that stream over 128 vectors at the price of one extra
 // read of X per phase.  Measured on MI355X (bf16 / fp16): at n hp = 2^18
-// (n = 4096, h = 64) Q X takes 1.40 ms resident vs 1.56 ms streaming for
+// (n = 4096, h = 64) Q X takes 1.43 ms resident vs 1.64 ms streaming for
 // 2^18 vectors; at n hp = 2^20 (n = 8192, h = 128) Q diag(lam) Q^T X takes
-// 1.66 ms vs 1.35 ms for 2^16 vectors.  A pass that only emits the
+// 1.66 ms vs 1.19 ms for 2^16 vectors.  A pass that only emits the
 // backward's coefficients reads X once in either kernel, and streams faster.
 bool wy_stream_selected(const WyShape &s, const WyArgs &a) {
     // 32-bit buffer offsets: a tile of 256 vectors and the coefficient rows
