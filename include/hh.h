@@ -41,7 +41,8 @@
  * and data of that same type.  The WY algorithm (compact form Q = I - Y T Y^T,
  * prior art of Bischof & Van Loan and Schreiber & Van Loan, not the paper)
  * computes in BF16 or F16 on the matrix cores with FP32 accumulation, F32
- * parameters, and BF16/F16 (matching compute) or F32 data.  HH_ALGO_AUTO picks
+ * parameters, and data in the compute type (BF16 or F16; F32 data is not
+ * converted on load and returns HH_ERR_UNSUPPORTED).  HH_ALGO_AUTO picks
  * FUSED for F64/F32 compute and WY for BF16/F16 compute.  Any other
  * combination returns HH_ERR_UNSUPPORTED.
  *

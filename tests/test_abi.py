@@ -69,6 +69,9 @@ def test_unsupported_combinations():
     assert _apply(_desc(p=L.HH_F64, io=L.HH_BF16, c=L.HH_BF16)) == L.HH_ERR_UNSUPPORTED
     # FUSED forced on a 16-bit compute type
     assert _apply(_desc(c=L.HH_BF16, algo=L.HH_ALGO_FUSED)) == L.HH_ERR_UNSUPPORTED
+    # WY reads and writes data in its 16-bit compute type only
+    assert _apply(_desc(n=64, h=4, p=L.HH_F32, io=L.HH_F32, c=L.HH_BF16)) == L.HH_ERR_UNSUPPORTED
+    assert _apply(_desc(n=64, h=4, p=L.HH_F32, io=L.HH_F16, c=L.HH_BF16)) == L.HH_ERR_UNSUPPORTED
     # fused kernels cover n <= 8192 (FP32)
     assert _apply(_desc(n=8193), ldu=8193, ldx=8193, ldy=8193) == L.HH_ERR_UNSUPPORTED
 
