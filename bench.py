@@ -160,12 +160,12 @@ def main():
             P.sym_raw(U, lam, X, compute=tdt, out=Y)
         elif op == "mahal":
             P.mahal_raw(U, lam, X, Xb)
-        elif op == "apply_fb":
-            P.apply_raw(U, X, compute=tdt, out=Y)
-            P.apply_bwd_raw(U, X, Gd, compute=tdt)
+        elif op == "apply_fb":  # the forward keeps its WY coefficients for the backward
+            _, rec = P.apply_raw(U, X, compute=tdt, out=Y, save=True)
+            P.apply_bwd_raw(U, X, Gd, compute=tdt, saved=rec)
         elif op == "sym_fb":
-            P.sym_raw(U, lam, X, compute=tdt, out=Y)
-            P.sym_bwd_raw(U, lam, X, Gd, compute=tdt)
+            _, rec = P.sym_raw(U, lam, X, compute=tdt, out=Y, save=True)
+            P.sym_bwd_raw(U, lam, X, Gd, compute=tdt, saved=rec)
         else:
             P.mahal_raw(U, lam, X, Xb)
             P.mahal_bwd_raw(U, lam, X, Xb, w, need_dX=False)
@@ -290,11 +290,11 @@ def main():
         S = min(N, 256)
         Xs, Gs = X[:S], Gd[:S]
         if op == "apply_fb":
-            dXg, dUg = P.apply_bwd_raw(U, Xs, Gs, compute=tdt)
-            Yg = P.apply_raw(U, Xs, compute=tdt)
+            Yg, rg = P.apply_raw(U, Xs, compute=tdt, save=True)
+            dXg, dUg = P.apply_bwd_raw(U, Xs, Gs, compute=tdt, saved=rg)
         else:
-            dXg, dUg, dlg = P.sym_bwd_raw(U, lam, Xs, Gs, compute=tdt)
-            Yg = P.sym_raw(U, lam, Xs, compute=tdt)
+            Yg, rg = P.sym_raw(U, lam, Xs, compute=tdt, save=True)
+            dXg, dUg, dlg = P.sym_bwd_raw(U, lam, Xs, Gs, compute=tdt, saved=rg)
         torch.cuda.synchronize()
         xh, gh = Xs.double().cpu().numpy(), Gs.double().cpu().numpy()
         t = time.perf_counter()

@@ -23,7 +23,8 @@ HH_ALGO_AUTO, HH_ALGO_FUSED, HH_ALGO_WY = range(3)
 EXPORTS = (
     "hh_workspace_size", "hh_apply", "hh_apply_T", "hh_sym_apply", "hh_mahalanobis",
     "hh_apply_backward", "hh_apply_T_backward", "hh_sym_apply_backward",
-    "hh_mahalanobis_backward", "hh_status_string", "hh_last_error", "hh_version",
+    "hh_mahalanobis_backward", "hh_saved_size", "hh_forward_save", "hh_backward_saved",
+    "hh_status_string", "hh_last_error", "hh_version",
 )
 
 _TORCH_TO_HH = {torch.float64: HH_F64, torch.float32: HH_F32, torch.bfloat16: HH_BF16,
@@ -66,6 +67,9 @@ def lib():
         "hh_apply_T_backward": [D, P, I, P, I, P, I, P, I, P, I, P, S, P],
         "hh_sym_apply_backward": [D, P, I, P, P, I, P, I, P, I, P, I, P, P, S, P],
         "hh_mahalanobis_backward": [D, P, I, P, P, I, P, I, P, P, P, I, P, I, P, P, S, P],
+        "hh_saved_size": [ctypes.c_int, D, ctypes.POINTER(S)],
+        "hh_forward_save": [ctypes.c_int, D, P, I, P, P, I, P, I, P, S, P, S, P],
+        "hh_backward_saved": [ctypes.c_int, D, P, I, P, P, I, P, S, P, I, P, I, P, I, P, P, S, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -112,6 +116,13 @@ def ld(t: torch.Tensor) -> int:
 
 def stream_of(t: torch.Tensor):
     return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def saved_record(op: int, desc: HHDesc, device) -> torch.Tensor:
+    """Caller-owned buffer for the coefficient record of forward op `op` (WY only)."""
+    nbytes = ctypes.c_size_t(0)
+    check("hh_saved_size", lib().hh_saved_size(op, ctypes.byref(desc), ctypes.byref(nbytes)))
+    return torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
 
 
 def workspace(op: int, desc: HHDesc, device) -> torch.Tensor:

@@ -156,7 +156,7 @@ static int aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 static hh_status forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
                          const void *lam, const void *X, int64_t ldx, const void *Xb,
                          int64_t ldb, void *Y, int64_t ldy, void *ws, size_t ws_bytes,
-                         hipStream_t st) {
+                         hipStream_t st, void *saved = nullptr, size_t saved_bytes = 0) {
     Algo algo;
     HH_TRY(check_desc(d, &algo));
     const int64_t n = d->n, h = d->h, N = d->N;
@@ -164,7 +164,10 @@ static hh_status forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
     HH_TRY(check_ld(op == HH_OP_MAHAL ? "lda" : "ldx", ldx, n));
     if (op == HH_OP_MAHAL) HH_TRY(check_ld("ldb", ldb, n));
     else HH_TRY(check_ld("ldy", ldy, n));
-    if (algo == Algo::WY) return wy_forward(op, d, U, ldu, lam, X, ldx, Xb, ldb, Y, ldy, ws, ws_bytes, st);
+    if (algo == Algo::WY)
+        return wy_forward(op, d, U, ldu, lam, X, ldx, Xb, ldb, Y, ldy, saved, saved_bytes, ws,
+                          ws_bytes, st);
+    if (saved) return fail(HH_ERR_UNSUPPORTED, "a coefficient record exists on the WY path only");
 
     FusedPlan p;
     HH_TRY(make_fused_plan(d, &p));
@@ -221,7 +224,8 @@ static hh_status backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu
                           const void *lam, const void *X, int64_t ldx, const void *Xb,
                           int64_t ldb, const void *G, int64_t ldg, void *dX, void *dXb,
                           int64_t lddx, void *dU, int64_t lddu, void *dlam, void *ws,
-                          size_t ws_bytes, hipStream_t st) {
+                          size_t ws_bytes, hipStream_t st, const void *saved = nullptr,
+                          size_t saved_bytes = 0) {
     Algo algo;
     HH_TRY(check_desc(d, &algo));
     const int64_t n = d->n, h = d->h, N = d->N;
@@ -233,7 +237,8 @@ static hh_status backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu
     if (dU && h > 0) HH_TRY(check_ld("lddu", lddu, n));
     if (algo == Algo::WY)
         return wy_backward(op, d, U, ldu, lam, X, ldx, Xb, ldb, G, ldg, dX, dXb, lddx, dU, lddu,
-                           dlam, ws, ws_bytes, st);
+                           dlam, saved, saved_bytes, ws, ws_bytes, st);
+    if (saved) return fail(HH_ERR_UNSUPPORTED, "a coefficient record exists on the WY path only");
 
     FusedPlan p;
     HH_TRY(make_fused_bwd_plan(d, &p));
@@ -372,6 +377,40 @@ hh_status hh_mahalanobis_backward(const hh_desc *d, const void *U, int64_t ldu, 
                                   size_t ws_bytes, hipStream_t stream) {
     return backward(HH_OP_MAHAL_BWD, d, U, ldu, lam, Xa, lda, Xb, ldb, ddist, 0, dXa, dXb, lddx,
                     dU, lddu, dlam, ws, ws_bytes, stream);
+}
+
+hh_status hh_saved_size(hh_op op, const hh_desc *d, size_t *bytes) {
+    if (!bytes) return fail(HH_ERR_INVALID_ARG, "bytes must not be null");
+    if (op != HH_OP_APPLY && op != HH_OP_APPLY_T && op != HH_OP_SYM)
+        return fail(HH_ERR_INVALID_ARG, "op must be HH_OP_APPLY, HH_OP_APPLY_T or HH_OP_SYM");
+    Algo algo;
+    HH_TRY(check_desc(d, &algo));
+    if (algo != Algo::WY) return fail(HH_ERR_UNSUPPORTED, "a coefficient record exists on the WY path only");
+    return wy_saved_size(op, d, bytes);
+}
+
+hh_status hh_forward_save(hh_op op, const hh_desc *d, const void *U, int64_t ldu, const void *lam,
+                          const void *X, int64_t ldx, void *Y, int64_t ldy, void *saved,
+                          size_t saved_bytes, void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (op != HH_OP_APPLY && op != HH_OP_APPLY_T && op != HH_OP_SYM)
+        return fail(HH_ERR_INVALID_ARG, "op must be HH_OP_APPLY, HH_OP_APPLY_T or HH_OP_SYM");
+    HH_TRY(check_ptr("saved", saved));
+    return forward(op, d, U, ldu, op == HH_OP_SYM ? lam : nullptr, X, ldx, nullptr, 0, Y, ldy, ws,
+                   ws_bytes, stream, saved, saved_bytes);
+}
+
+hh_status hh_backward_saved(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
+                            const void *lam, const void *X, int64_t ldx, const void *saved,
+                            size_t saved_bytes, const void *dY, int64_t lddy, void *dX,
+                            int64_t lddx, void *dU, int64_t lddu, void *dlam, void *ws,
+                            size_t ws_bytes, hipStream_t stream) {
+    if (op != HH_OP_APPLY_BWD && op != HH_OP_APPLY_T_BWD && op != HH_OP_SYM_BWD)
+        return fail(HH_ERR_INVALID_ARG,
+                    "op must be HH_OP_APPLY_BWD, HH_OP_APPLY_T_BWD or HH_OP_SYM_BWD");
+    HH_TRY(check_ptr("saved", saved));
+    const bool sym = op == HH_OP_SYM_BWD;
+    return backward(op, d, U, ldu, sym ? lam : nullptr, X, ldx, nullptr, 0, dY, lddy, dX, nullptr,
+                    lddx, dU, lddu, sym ? dlam : nullptr, ws, ws_bytes, stream, saved, saved_bytes);
 }
 
 const char *hh_status_string(hh_status s) {

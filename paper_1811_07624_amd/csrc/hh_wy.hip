@@ -690,9 +690,21 @@ hh_status wy_workspace_size(hh_op op, const hh_desc *d, size_t *bytes) {
     return HH_OK;
 }
 
+hh_status wy_saved_size(hh_op op, const hh_desc *d, size_t *bytes) {
+    WyShape s;
+    if (!wy_shape(d->n, d->h, &s))
+        return set_error(HH_ERR_UNSUPPORTED, "WY path supports n <= 8192 and h <= 128");
+    if (op != HH_OP_APPLY && op != HH_OP_APPLY_T && op != HH_OP_SYM)
+        return set_error(HH_ERR_UNSUPPORTED, "a coefficient record exists for Q X, Q^T X and Q diag(lam) Q^T X");
+    const size_t m = op == HH_OP_SYM ? 2 * s.hp : s.hp;
+    *bytes = m * (size_t)wy_ldc(d->N) * 2;
+    return HH_OK;
+}
+
 hh_status wy_forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, const void *lam,
                      const void *X, int64_t ldx, const void *Xb, int64_t ldb, void *Y,
-                     int64_t ldy, void *ws, size_t ws_bytes, hipStream_t st) {
+                     int64_t ldy, void *saved, size_t saved_bytes, void *ws, size_t ws_bytes,
+                     hipStream_t st) {
     (void)Xb;
     (void)ldb;
     WyShape s;
@@ -707,7 +719,20 @@ hh_status wy_forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, con
         return set_error(HH_ERR_UNSUPPORTED,
                          "WY path needs n, ldx, ldy multiples of 8 and 16-byte aligned data");
     const WyWs w = wy_ws(s, n, op == HH_OP_SYM, false);
-    if (N == 0) return HH_OK;
+    const int m = op == HH_OP_SYM ? 2 * s.hp : s.hp;
+    if (saved) {
+        const size_t need = (size_t)m * wy_ldc(N) * 2;
+        if (saved_bytes < need)
+            return set_error(HH_ERR_INVALID_ARG, "saved record needs %zu bytes, got %zu", need, saved_bytes);
+        if (((uintptr_t)saved & 15) != 0)
+            return set_error(HH_ERR_INVALID_ARG, "saved record must be 16-byte aligned");
+    }
+    // the record's columns past N are zero (all of them when N = 0)
+    auto zero_saved = [&]() -> hh_status {
+        const hipError_t ez = saved ? wy_zero_pad(saved, m, N, wy_ldc(N), st) : hipSuccess;
+        return ez == hipSuccess ? HH_OK : set_error(HH_ERR_HIP, "WY zero fill: %s", hipGetErrorString(ez));
+    };
+    if (N == 0) return zero_saved();
     if (h > 0 && !U) return set_error(HH_ERR_INVALID_ARG, "U must not be null");
     if (!X || !Y) return set_error(HH_ERR_INVALID_ARG, "X and Y must not be null");
     if (op == HH_OP_SYM && !lam) return set_error(HH_ERR_INVALID_ARG, "lam must not be null");
@@ -715,6 +740,7 @@ hh_status wy_forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, con
     if (!ws) return set_error(HH_ERR_INVALID_ARG, "ws must not be null");
     if (ws_bytes < w.total)
         return set_error(HH_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", w.total, ws_bytes);
+    if (zero_saved() != HH_OK) return HH_ERR_HIP;
     char *base = static_cast<char *>(ws);
     const bool bf = d->compute_dtype == HH_BF16;
     WyArgs a{};
@@ -730,6 +756,8 @@ hh_status wy_forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, con
     a.Tm = reinterpret_cast<const float *>(base + w.tm);
     a.lam = reinterpret_cast<const float *>(base + w.lam);
     a.store = 1;
+    a.coef = saved;
+    a.ldc = wy_ldc(N);
     a.n = (int)n;
     a.npad = s.npad;
     a.N = N;

@@ -393,7 +393,7 @@ BwdLayout bwd_layout(hh_op op, const WyShape &s, int64_t n, int64_t N) {
     BwdLayout L{};
     const bool sym = op == HH_OP_SYM_BWD;
     L.base = wy_ws(s, n, sym, true);
-    L.ldc = std::max<int64_t>(32, (N + 31) / 32 * 32);
+    L.ldc = wy_ldc(N);
     L.m = sym ? 2 * s.hp : s.hp;
     const int rowblocks = s.npad / kRankRows;
     const int64_t steps = std::max<int64_t>(1, (N + 31) / 32);
@@ -423,15 +423,15 @@ BwdLayout bwd_layout(hh_op op, const WyShape &s, int64_t n, int64_t N) {
 }
 
 template <typename E>
-hipError_t launch_products(const WyShape &s, const BwdLayout &L, char *ws, const void *G,
-                           int64_t ldg, const void *X, int64_t ldx, int64_t N, int n, bool sym,
-                           hipStream_t st) {
+hipError_t launch_products(const WyShape &s, const BwdLayout &L, char *ws, const char *cgp,
+                           const void *G, int64_t ldg, const void *X, int64_t ldx, int64_t N,
+                           int n, bool sym, hipStream_t st) {
     RankArgs ra{};
     ra.D[0] = G;
     ra.ld[0] = ldg;
     ra.D[1] = X;
     ra.ld[1] = ldx;
-    ra.C[0] = ws + L.cg;
+    ra.C[0] = cgp;
     ra.C[1] = ws + L.cx;
     ra.ldc = L.ldc;
     ra.out = reinterpret_cast<float *>(ws + L.part);
@@ -452,7 +452,7 @@ hipError_t launch_products(const WyShape &s, const BwdLayout &L, char *ws, const
     if (e != hipSuccess) return e;
     GramArgs ga{};
     const size_t hpb = (size_t)s.hp * L.ldc * 2;  // bytes of HP coefficient rows
-    char *cg = ws + L.cg, *cx = ws + L.cx;
+    const char *cg = cgp, *cx = ws + L.cx;
     if (sym) {  // K1 = B2 A1^T, K2 = B1 A1^T, K3 = B2 A2^T
         ga.P[0] = cx; ga.Q[0] = cg;
         ga.P[1] = cx + hpb; ga.Q[1] = cg;
@@ -476,10 +476,19 @@ size_t wy_bwd_ws_bytes(hh_op op, const WyShape &s, int64_t n, int64_t N) {
     return bwd_layout(op, s, n, N).total;
 }
 
+hipError_t wy_zero_pad(void *rows, int m, int64_t N, int64_t ldc, hipStream_t st) {
+    const int64_t padn = (int64_t)m * (ldc - N);
+    if (padn <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_zero_cols<unsigned short>), dim3((unsigned)((padn + 255) / 256)), dim3(256), 0,
+                       st, static_cast<unsigned short *>(rows), m, N, ldc);
+    return hipGetLastError();
+}
+
 hh_status wy_backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, const void *lam,
                       const void *X, int64_t ldx, const void *Xb, int64_t ldb, const void *G,
                       int64_t ldg, void *dX, void *dXb, int64_t lddx, void *dU, int64_t lddu,
-                      void *dlam, void *ws, size_t ws_bytes, hipStream_t st) {
+                      void *dlam, const void *saved, size_t saved_bytes, void *ws,
+                      size_t ws_bytes, hipStream_t st) {
     (void)Xb;
     (void)ldb;
     (void)dXb;
@@ -504,6 +513,13 @@ hh_status wy_backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, co
     if (!ws) return set_error(HH_ERR_INVALID_ARG, "ws must not be null");
     if (ws_bytes < L.total)
         return set_error(HH_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", L.total, ws_bytes);
+    if (saved) {
+        const size_t need = (size_t)L.m * L.ldc * 2;
+        if (saved_bytes < need)
+            return set_error(HH_ERR_INVALID_ARG, "saved record needs %zu bytes, got %zu", need, saved_bytes);
+        if (((uintptr_t)saved & 15) != 0)
+            return set_error(HH_ERR_INVALID_ARG, "saved record must be 16-byte aligned");
+    }
     const bool want_params = dU || (sym && dlam);
     if (!want_params && (!dX || N == 0)) return HH_OK;
 
@@ -542,26 +558,21 @@ hh_status wy_backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, co
                                 sym ? static_cast<const float *>(lam) : nullptr, want_m, base, L.base,
                                 true, st);
     if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY setup launch: %s", hipGetErrorString(e));
-    const int64_t padn = (int64_t)L.m * (L.ldc - N);
-    if (padn > 0) {
-        const dim3 zg((unsigned)((padn + 255) / 256));
-        if (bf) {
-            hipLaunchKernelGGL((k_zero_cols<__bf16>), zg, dim3(256), 0, st, reinterpret_cast<__bf16 *>(base + L.cg), L.m, N, L.ldc);
-            hipLaunchKernelGGL((k_zero_cols<__bf16>), zg, dim3(256), 0, st, reinterpret_cast<__bf16 *>(base + L.cx), L.m, N, L.ldc);
-        } else {
-            hipLaunchKernelGGL((k_zero_cols<_Float16>), zg, dim3(256), 0, st, reinterpret_cast<_Float16 *>(base + L.cg), L.m, N, L.ldc);
-            hipLaunchKernelGGL((k_zero_cols<_Float16>), zg, dim3(256), 0, st, reinterpret_cast<_Float16 *>(base + L.cx), L.m, N, L.ldc);
-        }
-    }
-    if (want_params) {
+    // coefficient rows of the pass over X: the caller's record of the
+    // forward, else formed here by a coefficient-only pass
+    const char *cgp = saved ? static_cast<const char *>(saved) : base + L.cg;
+    e = wy_zero_pad(base + L.cx, L.m, N, L.ldc, st);
+    if (e == hipSuccess && !saved) e = wy_zero_pad(base + L.cg, L.m, N, L.ldc, st);
+    if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY zero fill: %s", hipGetErrorString(e));
+    if (want_params && !saved) {
         e = wy_main_any(bf, s, xop, ax, st);
         if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY pass over X: %s", hipGetErrorString(e));
     }
     e = wy_main_any(bf, s, gop, ag, st);
     if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY pass over dY: %s", hipGetErrorString(e));
     if (!want_params) return HH_OK;
-    e = bf ? launch_products<BF16>(s, L, base, G, ldg, X, ldx, N, (int)n, sym, st)
-           : launch_products<F16>(s, L, base, G, ldg, X, ldx, N, (int)n, sym, st);
+    e = bf ? launch_products<BF16>(s, L, base, cgp, G, ldg, X, ldx, N, (int)n, sym, st)
+           : launch_products<F16>(s, L, base, cgp, G, ldg, X, ldx, N, (int)n, sym, st);
     if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY product launch: %s", hipGetErrorString(e));
     const int hp = s.hp;
     const int kind = op == HH_OP_APPLY_BWD ? 0 : op == HH_OP_APPLY_T_BWD ? 1 : 2;

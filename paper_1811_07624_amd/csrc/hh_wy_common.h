@@ -121,7 +121,10 @@ inline bool wy_shape(int64_t n, int64_t h, WyShape *s) {
 // Row segments of the partial Gram matrices (npad / 32 is a multiple of it).
 constexpr int kGramSeg = 16;
 
-// Workspace of the WY setup (shared by forward and backward).
+// Columns of a 16-bit coefficient row: N rounded up to 32 (at least 32); the
+// columns past N are zero.
+inline int64_t wy_ldc(int64_t N) { return N <= 32 ? 32 : (N + 31) / 32 * 32; }
+
 // Workspace of the WY path.  With lam (Q diag(lam) Q^T X) the Gram buffers
 // hold a second matrix after the first: gram -> [2][kGramSeg][hp][hp]
 // partials, gsum -> [2][hp][hp] (Y^T Y, then Y^T diag(lam) Y), and mf holds
@@ -167,5 +170,7 @@ hipError_t wy_stream_any(bool bf, const WyShape &s, WyOp op, const WyArgs &a, hi
 
 // Defined in hh_wy_bwd.hip.
 size_t wy_bwd_ws_bytes(hh_op op, const WyShape &s, int64_t n, int64_t N);
+// Zeroes columns N .. ldc-1 of m 16-bit coefficient rows (row stride ldc).
+hipError_t wy_zero_pad(void *rows, int m, int64_t N, int64_t ldc, hipStream_t st);
 
 }  // namespace hh

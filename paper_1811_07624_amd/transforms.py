@@ -9,9 +9,12 @@ returns; no arithmetic on the data happens in Python.
 
 ``compute`` selects the arithmetic: float64/float32 run the fused
 sequential-reflector kernels (data in that dtype); bfloat16/float16 run the
-compact-WY matrix-core kernels (data in that dtype or float32, parameters in
-float32).  ``algo`` may force "fused" or "wy"; the default "auto" follows
-``compute``.
+compact-WY matrix-core kernels (data in that dtype, parameters in float32).
+``algo`` may force "fused" or "wy"; the default "auto" follows ``compute``.
+
+On the WY path a forward whose reflectors (or spectrum) need a gradient keeps
+the per-vector WY coefficients (h scalars per vector, not h copies of the
+vector), and its backward uses them instead of a second pass over X.
 """
 from __future__ import annotations
 
@@ -55,7 +58,15 @@ def _check_dev(*ts):
 # --------------------------------------------------------------------------
 # raw calls (no autograd)
 # --------------------------------------------------------------------------
-def apply_raw(U, X, trans=False, compute=None, algo="auto", out=None):
+def is_wy(X, compute=None, algo="auto"):
+    """True when a call with these arguments runs the compact-WY kernels."""
+    comp = X.dtype if compute is None else compute
+    return algo == "wy" or (algo == "auto" and comp not in _FUSED)
+
+
+def apply_raw(U, X, trans=False, compute=None, algo="auto", out=None, save=False):
+    """Y = Q X (or Q^T X).  save=True (WY only) returns (Y, record) where the
+    record holds the coefficients apply_bwd_raw(..., saved=record) uses."""
     _check_dev(U, X)
     X = _rows(X)
     param, io, comp = _cfg(X, compute)
@@ -66,14 +77,22 @@ def apply_raw(U, X, trans=False, compute=None, algo="auto", out=None):
     Y = torch.empty((N, n), dtype=io, device=X.device) if out is None else out
     op = L.HH_OP_APPLY_T if trans else L.HH_OP_APPLY
     ws = L.workspace(op, desc, X.device)
+    ldu = max(n, U.stride(0) if h else n)
+    if save:
+        rec = L.saved_record(op, desc, X.device)
+        L.check("hh_forward_save", L.lib().hh_forward_save(
+            op, ctypes.byref(desc), L.ptr(U), ldu, None, L.ptr(X), L.ld(X), L.ptr(Y), L.ld(Y),
+            L.ptr(rec), rec.numel(), L.ptr(ws), ws.numel(), L.stream_of(X)))
+        return Y, rec
     fn = L.lib().hh_apply_T if trans else L.lib().hh_apply
     L.check("hh_apply_T" if trans else "hh_apply",
-            fn(ctypes.byref(desc), L.ptr(U), max(n, U.stride(0) if h else n), L.ptr(X), L.ld(X),
+            fn(ctypes.byref(desc), L.ptr(U), ldu, L.ptr(X), L.ld(X),
                L.ptr(Y), L.ld(Y), L.ptr(ws), ws.numel(), L.stream_of(X)))
     return Y
 
 
-def sym_raw(U, lam, X, compute=None, algo="auto", out=None):
+def sym_raw(U, lam, X, compute=None, algo="auto", out=None, save=False):
+    """Y = Q diag(lam) Q^T X.  save=True (WY only) returns (Y, record)."""
     _check_dev(U, lam, X)
     X = _rows(X)
     param, io, comp = _cfg(X, compute)
@@ -83,8 +102,15 @@ def sym_raw(U, lam, X, compute=None, algo="auto", out=None):
     desc = L.make_desc(n, h, N, param, io, comp, algo)
     Y = torch.empty((N, n), dtype=io, device=X.device) if out is None else out
     ws = L.workspace(L.HH_OP_SYM, desc, X.device)
+    ldu = max(n, U.stride(0) if h else n)
+    if save:
+        rec = L.saved_record(L.HH_OP_SYM, desc, X.device)
+        L.check("hh_forward_save", L.lib().hh_forward_save(
+            L.HH_OP_SYM, ctypes.byref(desc), L.ptr(U), ldu, L.ptr(lam), L.ptr(X), L.ld(X),
+            L.ptr(Y), L.ld(Y), L.ptr(rec), rec.numel(), L.ptr(ws), ws.numel(), L.stream_of(X)))
+        return Y, rec
     L.check("hh_sym_apply", L.lib().hh_sym_apply(
-        ctypes.byref(desc), L.ptr(U), max(n, U.stride(0) if h else n), L.ptr(lam), L.ptr(X),
+        ctypes.byref(desc), L.ptr(U), ldu, L.ptr(lam), L.ptr(X),
         L.ld(X), L.ptr(Y), L.ld(Y), L.ptr(ws), ws.numel(), L.stream_of(X)))
     return Y
 
@@ -105,7 +131,9 @@ def mahal_raw(U, lam, Xa, Xb, compute=None, algo="auto"):
     return d
 
 
-def apply_bwd_raw(U, X, dY, trans=False, compute=None, algo="auto", need_dX=True, need_dU=True):
+def apply_bwd_raw(U, X, dY, trans=False, compute=None, algo="auto", need_dX=True, need_dU=True,
+                  saved=None):
+    """Gradients of Y = Q X (or Q^T X); saved: the forward's record (WY only)."""
     _check_dev(U, X, dY)
     X, dY = _rows(X), _rows(dY.to(X.dtype))
     param, io, comp = _cfg(X, compute)
@@ -117,16 +145,25 @@ def apply_bwd_raw(U, X, dY, trans=False, compute=None, algo="auto", need_dX=True
     dU = torch.empty((h, n), dtype=param, device=X.device) if need_dU else None
     op = L.HH_OP_APPLY_T_BWD if trans else L.HH_OP_APPLY_BWD
     ws = L.workspace(op, desc, X.device)
+    ldu = max(n, U.stride(0) if h else n)
+    lddx = n if dX is None else L.ld(dX)
+    if saved is not None:
+        L.check("hh_backward_saved", L.lib().hh_backward_saved(
+            op, ctypes.byref(desc), L.ptr(U), ldu, None, L.ptr(X), L.ld(X), L.ptr(saved),
+            saved.numel(), L.ptr(dY), L.ld(dY), L.ptr(dX), lddx, L.ptr(dU), n, None,
+            L.ptr(ws), ws.numel(), L.stream_of(X)))
+        return dX, dU
     fn = L.lib().hh_apply_T_backward if trans else L.lib().hh_apply_backward
     L.check("hh_apply_T_backward" if trans else "hh_apply_backward",
-            fn(ctypes.byref(desc), L.ptr(U), max(n, U.stride(0) if h else n), L.ptr(X), L.ld(X),
-               L.ptr(dY), L.ld(dY), L.ptr(dX), n if dX is None else L.ld(dX), L.ptr(dU), n,
+            fn(ctypes.byref(desc), L.ptr(U), ldu, L.ptr(X), L.ld(X),
+               L.ptr(dY), L.ld(dY), L.ptr(dX), lddx, L.ptr(dU), n,
                L.ptr(ws), ws.numel(), L.stream_of(X)))
     return dX, dU
 
 
 def sym_bwd_raw(U, lam, X, dY, compute=None, algo="auto", need_dX=True, need_dU=True,
-                need_dlam=True):
+                need_dlam=True, saved=None):
+    """Gradients of Y = Q diag(lam) Q^T X; saved: the forward's record (WY only)."""
     _check_dev(U, lam, X, dY)
     X, dY = _rows(X), _rows(dY.to(X.dtype))
     param, io, comp = _cfg(X, compute)
@@ -138,9 +175,17 @@ def sym_bwd_raw(U, lam, X, dY, compute=None, algo="auto", need_dX=True, need_dU=
     dU = torch.empty((h, n), dtype=param, device=X.device) if need_dU else None
     dlam = torch.empty((n,), dtype=param, device=X.device) if need_dlam else None
     ws = L.workspace(L.HH_OP_SYM_BWD, desc, X.device)
+    ldu = max(n, U.stride(0) if h else n)
+    lddx = n if dX is None else L.ld(dX)
+    if saved is not None:
+        L.check("hh_backward_saved", L.lib().hh_backward_saved(
+            L.HH_OP_SYM_BWD, ctypes.byref(desc), L.ptr(U), ldu, L.ptr(lam), L.ptr(X), L.ld(X),
+            L.ptr(saved), saved.numel(), L.ptr(dY), L.ld(dY), L.ptr(dX), lddx, L.ptr(dU), n,
+            L.ptr(dlam), L.ptr(ws), ws.numel(), L.stream_of(X)))
+        return dX, dU, dlam
     L.check("hh_sym_apply_backward", L.lib().hh_sym_apply_backward(
-        ctypes.byref(desc), L.ptr(U), max(n, U.stride(0) if h else n), L.ptr(lam), L.ptr(X),
-        L.ld(X), L.ptr(dY), L.ld(dY), L.ptr(dX), n if dX is None else L.ld(dX), L.ptr(dU), n,
+        ctypes.byref(desc), L.ptr(U), ldu, L.ptr(lam), L.ptr(X),
+        L.ld(X), L.ptr(dY), L.ld(dY), L.ptr(dX), lddx, L.ptr(dU), n,
         L.ptr(dlam), L.ptr(ws), ws.numel(), L.stream_of(X)))
     return dX, dU, dlam
 
@@ -173,15 +218,21 @@ class _Apply(torch.autograd.Function):
     @staticmethod
     def forward(ctx, U, X, trans, compute, algo):
         ctx.cfg = (trans, compute, algo)
-        ctx.save_for_backward(U, X)
-        return apply_raw(U, X, trans, compute, algo)
+        rec = None
+        if ctx.needs_input_grad[0] and is_wy(X, compute, algo):
+            Y, rec = apply_raw(U, X, trans, compute, algo, save=True)
+        else:
+            Y = apply_raw(U, X, trans, compute, algo)
+        ctx.save_for_backward(U, X, rec)
+        return Y
 
     @staticmethod
     def backward(ctx, dY):
-        U, X = ctx.saved_tensors
+        U, X, rec = ctx.saved_tensors
         trans, compute, algo = ctx.cfg
         dX, dU = apply_bwd_raw(U, X, dY, trans, compute, algo,
-                               need_dX=ctx.needs_input_grad[1], need_dU=ctx.needs_input_grad[0])
+                               need_dX=ctx.needs_input_grad[1], need_dU=ctx.needs_input_grad[0],
+                               saved=rec)
         if dU is not None:
             dU = dU.to(U.dtype)
         return dU, dX, None, None, None
@@ -191,17 +242,22 @@ class _Sym(torch.autograd.Function):
     @staticmethod
     def forward(ctx, U, lam, X, compute, algo):
         ctx.cfg = (compute, algo)
-        ctx.save_for_backward(U, lam, X)
-        return sym_raw(U, lam, X, compute, algo)
+        rec = None
+        if (ctx.needs_input_grad[0] or ctx.needs_input_grad[1]) and is_wy(X, compute, algo):
+            Y, rec = sym_raw(U, lam, X, compute, algo, save=True)
+        else:
+            Y = sym_raw(U, lam, X, compute, algo)
+        ctx.save_for_backward(U, lam, X, rec)
+        return Y
 
     @staticmethod
     def backward(ctx, dY):
-        U, lam, X = ctx.saved_tensors
+        U, lam, X, rec = ctx.saved_tensors
         compute, algo = ctx.cfg
         dX, dU, dlam = sym_bwd_raw(U, lam, X, dY, compute, algo,
                                    need_dX=ctx.needs_input_grad[2],
                                    need_dU=ctx.needs_input_grad[0],
-                                   need_dlam=ctx.needs_input_grad[1])
+                                   need_dlam=ctx.needs_input_grad[1], saved=rec)
         if dU is not None:
             dU = dU.to(U.dtype)
         if dlam is not None:

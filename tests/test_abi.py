@@ -110,3 +110,54 @@ def test_workspace_size_all_ops():
 def test_status_strings():
     for s in range(5):
         assert P.lib().hh_status_string(s)
+
+
+def _wy_desc(n=256, h=12, N=100, c=L.HH_BF16):
+    return L.HHDesc(n, h, N, L.HH_F32, c, c, L.HH_ALGO_AUTO)
+
+
+def test_saved_size():
+    nb = ctypes.c_size_t(0)
+    lib = P.lib()
+    # m = h rounded up to 64 (128 for h > 64), doubled for the symmetric form;
+    # row stride = N rounded up to 32
+    for (n, h, N, op, m) in [(256, 12, 100, L.HH_OP_APPLY, 64), (256, 12, 100, L.HH_OP_APPLY_T, 64),
+                             (256, 12, 100, L.HH_OP_SYM, 128), (8192, 100, 1, L.HH_OP_SYM, 256),
+                             (1024, 64, 0, L.HH_OP_APPLY, 64)]:
+        d = _wy_desc(n, h, N)
+        assert lib.hh_saved_size(op, ctypes.byref(d), ctypes.byref(nb)) == L.HH_OK
+        assert nb.value == m * max(32, (N + 31) // 32 * 32) * 2
+    d = _wy_desc()
+    assert lib.hh_saved_size(L.HH_OP_MAHAL, ctypes.byref(d), ctypes.byref(nb)) == L.HH_ERR_INVALID_ARG
+    assert lib.hh_saved_size(L.HH_OP_APPLY_BWD, ctypes.byref(d), ctypes.byref(nb)) == L.HH_ERR_INVALID_ARG
+    # the fused backward keeps no coefficients
+    assert lib.hh_saved_size(L.HH_OP_APPLY, ctypes.byref(_desc()), ctypes.byref(nb)) == L.HH_ERR_UNSUPPORTED
+
+
+def test_saved_record_validation():
+    # fake, 16-byte aligned pointers: every failure below is caught before any launch
+    v = ctypes.c_void_p
+    lib = P.lib()
+    d = _wy_desc()
+    nb, ws = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    lib.hh_saved_size(L.HH_OP_APPLY, ctypes.byref(d), ctypes.byref(nb))
+    lib.hh_workspace_size(L.HH_OP_APPLY, ctypes.byref(d), ctypes.byref(ws))
+
+    def fwd(op=L.HH_OP_APPLY, saved=4096, sb=nb.value, desc=d):
+        return lib.hh_forward_save(op, ctypes.byref(desc), v(1024), 256, None, v(2048), 256, v(3072),
+                                   256, v(saved) if saved else None, sb, v(8192), ws.value, None)
+    assert fwd(saved=0) == L.HH_ERR_INVALID_ARG
+    assert fwd(sb=nb.value - 1) == L.HH_ERR_INVALID_ARG
+    assert fwd(saved=4100) == L.HH_ERR_INVALID_ARG            # not 16-byte aligned
+    assert fwd(op=L.HH_OP_MAHAL) == L.HH_ERR_INVALID_ARG
+    assert fwd(desc=_desc()) == L.HH_ERR_UNSUPPORTED           # fused path
+
+    def bwd(op=L.HH_OP_APPLY_BWD, saved=4096, sb=nb.value, desc=d):
+        return lib.hh_backward_saved(op, ctypes.byref(desc), v(1024), 256, None, v(2048), 256,
+                                     v(saved) if saved else None, sb, v(3072), 256, v(5120), 256,
+                                     v(6144), 256, None, v(8192), 1 << 40, None)
+    assert bwd(saved=0) == L.HH_ERR_INVALID_ARG
+    assert bwd(op=L.HH_OP_APPLY) == L.HH_ERR_INVALID_ARG
+    assert bwd(sb=nb.value - 1) == L.HH_ERR_INVALID_ARG
+    assert bwd(saved=4104) == L.HH_ERR_INVALID_ARG
+    assert bwd(desc=_desc()) == L.HH_ERR_UNSUPPORTED

@@ -248,3 +248,81 @@ def test_wy_autograd():
     _, rdU, rdlam = oracle.sym_bwd(host(U), host(lam), host(X), host(G))
     assert rel_fro(host(U.grad), rdU) < TOL16
     assert rel_fro(host(lam.grad), rdlam) < TOL16
+
+
+# ----------------------------------------------------------------------------
+# coefficient record of the forward, taken by the backward
+# ----------------------------------------------------------------------------
+# resident kernel (n * hp < 2^19) and streaming kernel, ragged N
+SAVED_SHAPES = [(512, 9, 100), (4096, 64, 300), (8192, 128, 48), (2048, 100, 33), (64, 1, 7)]
+
+
+@pytest.mark.parametrize("dname", ["bf16", "f16"])
+@pytest.mark.parametrize("n,h,N", SAVED_SHAPES)
+@pytest.mark.parametrize("kind", ["apply", "apply_T", "sym"])
+def test_wy_saved_record(dname, n, h, N, kind):
+    dt = DT[dname]
+    U, X = make(n, h, N, dt, seed=11 * n + h)
+    Uraw = U * torch.linspace(0.5, 2.0, h, device=dev())[:, None]
+    lam = torch.tensor(synth.eig_loguniform(n, seed=3), dtype=torch.float32, device=dev())
+    G = torch.tensor(synth.gaussian((N, n), seed=4, stream=synth.STREAM_G), dtype=torch.float32,
+                     device=dev()).to(dt)
+    if kind == "sym":
+        Y0 = P.sym_raw(Uraw, lam, X, compute=dt)
+        Y, rec = P.sym_raw(Uraw, lam, X, compute=dt, save=True)
+        dX, dU, dlam = P.sym_bwd_raw(Uraw, lam, X, G, compute=dt, saved=rec)
+        dX0, dU0, dlam0 = P.sym_bwd_raw(Uraw, lam, X, G, compute=dt)
+        rdX, rdU, rdlam = oracle.sym_bwd(host(Uraw), host(lam), host(X), host(G))
+        m = 2 * (64 if h <= 64 else 128)
+    else:
+        tr = kind == "apply_T"
+        Y0 = P.apply_raw(Uraw, X, trans=tr, compute=dt)
+        Y, rec = P.apply_raw(Uraw, X, trans=tr, compute=dt, save=True)
+        dX, dU = P.apply_bwd_raw(Uraw, X, G, trans=tr, compute=dt, saved=rec)
+        dX0, dU0 = P.apply_bwd_raw(Uraw, X, G, trans=tr, compute=dt)
+        rdX, rdU = oracle.apply_bwd(host(Uraw), host(X), host(G), trans=tr)
+        m = 64 if h <= 64 else 128
+    torch.cuda.synchronize()
+    # writing the record leaves the forward's output unchanged, bit for bit
+    assert torch.equal(Y, Y0)
+    ldc = max(32, (N + 31) // 32 * 32)
+    assert rec.numel() == m * ldc * 2
+    cols = rec.view(torch.int16).view(m, ldc)
+    assert torch.count_nonzero(cols[:, N:]) == 0
+    # dX comes from the pass over dY alone
+    assert torch.equal(dX, dX0)
+    assert rel_rows(host(dX), rdX) < TOL16
+    assert rel_fro(host(dU), rdU) < TOL16, rel_fro(host(dU), rdU)
+    assert rel_fro(host(dU), host(dU0)) < 1e-2
+    if kind == "sym":
+        assert rel_fro(host(dlam), rdlam) < TOL16
+        assert rel_fro(host(dlam), host(dlam0)) < 1e-2
+
+
+def test_wy_saved_record_empty_batch():
+    dt = torch.bfloat16
+    n = 256
+    U, _ = make(n, 6, 1, dt)
+    E = torch.empty((0, n), dtype=dt, device=dev())
+    Y, rec = P.apply_raw(U, E, compute=dt, save=True)
+    torch.cuda.synchronize()
+    assert Y.shape == (0, n) and rec.numel() == 64 * 32 * 2
+    assert torch.count_nonzero(rec) == 0
+    dX, dU = P.apply_bwd_raw(U, E, E, compute=dt, saved=rec)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(dU) == 0
+
+
+def test_wy_autograd_uses_record():
+    """apply/sym_apply keep the record when the reflectors need a gradient;
+    the gradients still match the oracle."""
+    dt = torch.float16
+    n, h, N = 1024, 40, 96
+    U, X = make(n, h, N, dt, seed=21)
+    U.requires_grad_(True)
+    G = torch.randn((N, n), device=dev()).to(dt)
+    Y = P.apply(U, X, compute=dt)
+    assert Y.grad_fn is not None
+    (Y.float() * G.float()).sum().backward()
+    _, rdU = oracle.apply_bwd(host(U), host(X), host(G))
+    assert rel_fro(host(U.grad), rdU) < TOL16
