@@ -168,18 +168,21 @@ HH_API hh_status hh_mahalanobis_backward(const hh_desc *d, const void *U, int64_
                                   size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
- * Saved coefficients (WY algorithm only; not in the paper).  The WY backward
+ * Saved forward record (WY algorithm only; not in the paper).  The WY backward
  * of Q X, Q^T X and Q diag(lam) Q^T X needs, per vector, the h coefficients
  * of its compact-WY forward: T Y^T x for Q x, T^T Y^T x for Q^T x, and for
- * the symmetric form both T^T Y^T x and T Y^T (diag(lam) Q^T x).  The plain
- * backward calls form them again by a pass over X; a forward that writes them
- * to a caller-owned record spares the backward that pass (h scalars per vector
- * are kept, not h copies of the vector).
+ * the symmetric form both T^T Y^T x and T Y^T (diag(lam) Q^T x); and it needs
+ * the reflector setup (normalised and rounded reflectors, T, the spectrum).
+ * The plain backward calls form both again, the coefficients by a pass over X.
+ * A forward that writes them to a caller-owned record spares the backward that
+ * pass and that setup (h scalars per vector are kept, not h copies of the
+ * vector).
  *
- * Record layout: m rows of 16-bit values in the compute type (m = h rounded
- * up to 64 or 128; twice that for the symmetric form), row stride ldc = N
- * rounded up to 32 (at least 32), columns past N zero.  It stays valid for
- * the same U, lam, X, n, h, N and dtypes.
+ * Record: 16-bit coefficient rows in the compute type (m = h rounded up to 64
+ * or 128, twice that for the symmetric form; row stride N rounded up to 32,
+ * at least 32; columns past N zero), followed by the setup.  Its contents are
+ * internal to the library; it stays valid for the same U, lam, X, n, h, N and
+ * dtypes.
  *
  * hh_saved_size: bytes of the record for forward op HH_OP_APPLY, HH_OP_APPLY_T
  * or HH_OP_SYM; HH_ERR_UNSUPPORTED for the fused algorithm, whose backward
@@ -188,20 +191,23 @@ HH_API hh_status hh_saved_size(hh_op op, const hh_desc *d, size_t *bytes);
 
 /* The forward op (HH_OP_APPLY, HH_OP_APPLY_T or HH_OP_SYM; lam is read for
  * HH_OP_SYM only, else ignored) with the same Y as hh_apply / hh_apply_T /
- * hh_sym_apply, which also writes the record to `saved` (device, non-null,
- * 16-byte aligned, saved_bytes >= hh_saved_size).  Workspace: that of the
- * forward op.  With N == 0 the record is zeroed and nothing else is done. */
+ * hh_sym_apply, which also fills the record `saved` (device, non-null,
+ * 16-byte aligned, saved_bytes >= hh_saved_size).  The record takes the place
+ * of the workspace: ws may be null and ws_bytes 0.  With N == 0 only the setup
+ * is recorded. */
 HH_API hh_status hh_forward_save(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
                           const void *lam, const void *X, int64_t ldx, void *Y,
                           int64_t ldy, void *saved, size_t saved_bytes, void *ws,
                           size_t ws_bytes, hipStream_t stream);
 
 /* The backward op (HH_OP_APPLY_BWD, HH_OP_APPLY_T_BWD or HH_OP_SYM_BWD) from
- * the record hh_forward_save wrote for the matching forward op on the same
+ * the record hh_forward_save filled for the matching forward op on the same
  * inputs: the results of hh_apply_backward / hh_apply_T_backward /
- * hh_sym_apply_backward (lam and dlam are used for HH_OP_SYM_BWD only) without
- * their pass over X.  X is still read: dU needs it.  Workspace: that of the
- * backward op.  A record of other inputs gives wrong gradients, not an error. */
+ * hh_sym_apply_backward (lam and dlam are used for HH_OP_SYM_BWD only; U and
+ * lam are validated, their setup is taken from the record) without their pass
+ * over X and their setup.  X is still read: dU needs it.  Workspace: that of
+ * the backward op.  A record of other inputs gives wrong gradients, not an
+ * error. */
 HH_API hh_status hh_backward_saved(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
                             const void *lam, const void *X, int64_t ldx,
                             const void *saved, size_t saved_bytes, const void *dY,

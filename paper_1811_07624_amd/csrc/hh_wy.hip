@@ -696,8 +696,7 @@ hh_status wy_saved_size(hh_op op, const hh_desc *d, size_t *bytes) {
         return set_error(HH_ERR_UNSUPPORTED, "WY path supports n <= 8192 and h <= 128");
     if (op != HH_OP_APPLY && op != HH_OP_APPLY_T && op != HH_OP_SYM)
         return set_error(HH_ERR_UNSUPPORTED, "a coefficient record exists for Q X, Q^T X and Q diag(lam) Q^T X");
-    const size_t m = op == HH_OP_SYM ? 2 * s.hp : s.hp;
-    *bytes = m * (size_t)wy_ldc(d->N) * 2;
+    *bytes = wy_record(s, d->n, d->N, op == HH_OP_SYM).total;
     return HH_OK;
 }
 
@@ -718,30 +717,35 @@ hh_status wy_forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, con
     if (n % 8 != 0 || ldx % 8 != 0 || ldy % 8 != 0 || ((uintptr_t)X & 15) || ((uintptr_t)Y & 15))
         return set_error(HH_ERR_UNSUPPORTED,
                          "WY path needs n, ldx, ldy multiples of 8 and 16-byte aligned data");
-    const WyWs w = wy_ws(s, n, op == HH_OP_SYM, false);
-    const int m = op == HH_OP_SYM ? 2 * s.hp : s.hp;
+    const bool sym = op == HH_OP_SYM;
+    const WyRecord rec = wy_record(s, n, N, sym);
     if (saved) {
-        const size_t need = (size_t)m * wy_ldc(N) * 2;
-        if (saved_bytes < need)
-            return set_error(HH_ERR_INVALID_ARG, "saved record needs %zu bytes, got %zu", need, saved_bytes);
+        if (saved_bytes < rec.total)
+            return set_error(HH_ERR_INVALID_ARG, "saved record needs %zu bytes, got %zu", rec.total, saved_bytes);
         if (((uintptr_t)saved & 15) != 0)
             return set_error(HH_ERR_INVALID_ARG, "saved record must be 16-byte aligned");
     }
-    // the record's columns past N are zero (all of them when N = 0)
-    auto zero_saved = [&]() -> hh_status {
-        const hipError_t ez = saved ? wy_zero_pad(saved, m, N, wy_ldc(N), st) : hipSuccess;
-        return ez == hipSuccess ? HH_OK : set_error(HH_ERR_HIP, "WY zero fill: %s", hipGetErrorString(ez));
-    };
-    if (N == 0) return zero_saved();
+    // Without a record N = 0 is a no-op; with one, the setup is still
+    // recorded for the backward.
+    if (N == 0 && !saved) return HH_OK;
     if (h > 0 && !U) return set_error(HH_ERR_INVALID_ARG, "U must not be null");
-    if (!X || !Y) return set_error(HH_ERR_INVALID_ARG, "X and Y must not be null");
-    if (op == HH_OP_SYM && !lam) return set_error(HH_ERR_INVALID_ARG, "lam must not be null");
-    if (Y == X && ldy != ldx) return set_error(HH_ERR_INVALID_ARG, "in-place call needs ldy == ldx");
-    if (!ws) return set_error(HH_ERR_INVALID_ARG, "ws must not be null");
-    if (ws_bytes < w.total)
-        return set_error(HH_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", w.total, ws_bytes);
-    if (zero_saved() != HH_OK) return HH_ERR_HIP;
-    char *base = static_cast<char *>(ws);
+    if (N > 0 && (!X || !Y)) return set_error(HH_ERR_INVALID_ARG, "X and Y must not be null");
+    if (sym && !lam) return set_error(HH_ERR_INVALID_ARG, "lam must not be null");
+    if (N > 0 && Y == X && ldy != ldx) return set_error(HH_ERR_INVALID_ARG, "in-place call needs ldy == ldx");
+    // The setup goes to the record when there is one (the workspace is then
+    // not touched), else to the workspace.
+    const WyWs w = wy_ws(s, n, sym, saved != nullptr);
+    if (!saved) {
+        if (!ws) return set_error(HH_ERR_INVALID_ARG, "ws must not be null");
+        const size_t need = w.total;
+        if (ws_bytes < need)
+            return set_error(HH_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", need, ws_bytes);
+    }
+    char *base = saved ? static_cast<char *>(saved) + rec.setup : static_cast<char *>(ws);
+    if (saved) {  // the record's coefficient columns past N are zero
+        const hipError_t ez = wy_zero_pad(saved, rec.m, N, rec.ldc, st);
+        if (ez != hipSuccess) return set_error(HH_ERR_HIP, "WY zero fill: %s", hipGetErrorString(ez));
+    }
     const bool bf = d->compute_dtype == HH_BF16;
     WyArgs a{};
     a.X = X;
@@ -757,15 +761,17 @@ hh_status wy_forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, con
     a.lam = reinterpret_cast<const float *>(base + w.lam);
     a.store = 1;
     a.coef = saved;
-    a.ldc = wy_ldc(N);
+    a.ldc = rec.ldc;
     a.n = (int)n;
     a.npad = s.npad;
     a.N = N;
-    const bool sym = op == HH_OP_SYM;
+    // A record serves any backward pass, so it holds Y^T diag(lam) Y (used by
+    // the streaming kernel) and the FP64 reflectors whenever they may be needed.
     hipError_t e = wy_setup_any(bf, s, static_cast<const float *>(U), ldu, n, h,
                                 sym ? static_cast<const float *>(lam) : nullptr,
-                                sym && wy_stream_selected(s, a), base, w, false, st);
+                                sym && (saved || wy_stream_selected(s, a)), base, w, saved != nullptr, st);
     if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY setup launch: %s", hipGetErrorString(e));
+    if (N == 0) return HH_OK;
     const WyOp wop = op == HH_OP_APPLY ? W_APPLY : op == HH_OP_APPLY_T ? W_APPLY_T : W_SYM;
     e = wy_main_any(bf, s, wop, a, st);
     if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY kernel launch: %s", hipGetErrorString(e));

@@ -513,10 +513,10 @@ hh_status wy_backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, co
     if (!ws) return set_error(HH_ERR_INVALID_ARG, "ws must not be null");
     if (ws_bytes < L.total)
         return set_error(HH_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", L.total, ws_bytes);
+    const WyRecord rec = wy_record(s, n, N, sym);
     if (saved) {
-        const size_t need = (size_t)L.m * L.ldc * 2;
-        if (saved_bytes < need)
-            return set_error(HH_ERR_INVALID_ARG, "saved record needs %zu bytes, got %zu", need, saved_bytes);
+        if (saved_bytes < rec.total)
+            return set_error(HH_ERR_INVALID_ARG, "saved record needs %zu bytes, got %zu", rec.total, saved_bytes);
         if (((uintptr_t)saved & 15) != 0)
             return set_error(HH_ERR_INVALID_ARG, "saved record must be 16-byte aligned");
     }
@@ -524,15 +524,18 @@ hh_status wy_backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, co
     if (!want_params && (!dX || N == 0)) return HH_OK;
 
     char *base = static_cast<char *>(ws);
+    // the forward's setup (normalised reflectors, T, spectrum) from the record,
+    // else formed here in the workspace
+    char *sb = saved ? const_cast<char *>(static_cast<const char *>(saved)) + rec.setup : base;
     const bool bf = d->compute_dtype == HH_BF16;
     WyArgs a{};
-    a.Yc = base + L.base.yc;
-    a.Yr = base + L.base.yr;
-    a.Ycs = base + L.base.ycs;
-    a.Tf = base + L.base.tf;
-    a.Mf = base + L.base.mf;
-    a.Tm = reinterpret_cast<const float *>(base + L.base.tm);
-    a.lam = reinterpret_cast<const float *>(base + L.base.lam);
+    a.Yc = sb + L.base.yc;
+    a.Yr = sb + L.base.yr;
+    a.Ycs = sb + L.base.ycs;
+    a.Tf = sb + L.base.tf;
+    a.Mf = sb + L.base.mf;
+    a.Tm = reinterpret_cast<const float *>(sb + L.base.tm);
+    a.lam = reinterpret_cast<const float *>(sb + L.base.lam);
     a.ldc = L.ldc;
     a.n = (int)n;
     a.npad = s.npad;
@@ -554,10 +557,12 @@ hh_status wy_backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, co
     ag.coef = want_params ? base + L.cx : nullptr;
     ag.store = dX ? 1 : 0;
     const bool want_m = sym && ((want_params && wy_stream_selected(s, ax)) || wy_stream_selected(s, ag));
-    hipError_t e = wy_setup_any(bf, s, static_cast<const float *>(U), ldu, n, h,
-                                sym ? static_cast<const float *>(lam) : nullptr, want_m, base, L.base,
-                                true, st);
-    if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY setup launch: %s", hipGetErrorString(e));
+    hipError_t e = hipSuccess;
+    if (!saved) {
+        e = wy_setup_any(bf, s, static_cast<const float *>(U), ldu, n, h,
+                         sym ? static_cast<const float *>(lam) : nullptr, want_m, base, L.base, true, st);
+        if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY setup launch: %s", hipGetErrorString(e));
+    }
     // coefficient rows of the pass over X: the caller's record of the
     // forward, else formed here by a coefficient-only pass
     const char *cgp = saved ? static_cast<const char *>(saved) : base + L.cg;
@@ -597,11 +602,11 @@ hh_status wy_backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, co
     ca.part = reinterpret_cast<const double *>(base + L.psum);
     ca.gx = sym ? reinterpret_cast<const double *>(base + L.gxsum) : nullptr;
     ca.m = L.m;
-    ca.uh = reinterpret_cast<const double *>(base + L.base.uh64);
+    ca.uh = reinterpret_cast<const double *>(sb + L.base.uh64);
     ca.Ma = reinterpret_cast<const double *>(base + L.ma);
     ca.Mb = reinterpret_cast<const double *>(base + L.mb);
     ca.Mc = reinterpret_cast<const double *>(base + L.mc);
-    ca.lam = reinterpret_cast<const float *>(base + L.base.lam);
+    ca.lam = reinterpret_cast<const float *>(sb + L.base.lam);
     ca.dV = reinterpret_cast<double *>(base + L.dv);
     ca.dlam = sym ? static_cast<float *>(dlam) : nullptr;
     ca.n = (int)n;
@@ -613,8 +618,8 @@ hh_status wy_backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, co
     if (dU && h > 0)
         hipLaunchKernelGGL(k_wy_finish, dim3((unsigned)h), dim3(256), 0, st,
                            reinterpret_cast<const double *>(base + L.dv), s.npad, (int)n,
-                           reinterpret_cast<const double *>(base + L.base.uh64),
-                           reinterpret_cast<const double *>(base + L.base.nrmraw), static_cast<float *>(dU),
+                           reinterpret_cast<const double *>(sb + L.base.uh64),
+                           reinterpret_cast<const double *>(sb + L.base.nrmraw), static_cast<float *>(dU),
                            lddu);
     e = hipGetLastError();
     if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY finish launch: %s", hipGetErrorString(e));

@@ -155,6 +155,25 @@ inline WyWs wy_ws(const WyShape &s, int64_t n, bool with_lam, bool bwd) {
     return w;
 }
 
+// Coefficient record of a forward (hh_forward_save): m = HP (2 HP for the
+// symmetric form) 16-bit coefficient rows of ldc = wy_ldc(N) columns, then,
+// from a 256-byte aligned offset, the forward's setup laid out as
+// wy_ws(s, n, sym, true) (reflector copies, T fragments, the spectrum and the
+// FP64 normalised reflectors the backward's chain rule needs).
+struct WyRecord {
+    int m;
+    int64_t ldc;
+    size_t setup, total;
+};
+inline WyRecord wy_record(const WyShape &s, int64_t n, int64_t N, bool sym) {
+    WyRecord r{};
+    r.m = sym ? 2 * s.hp : s.hp;
+    r.ldc = wy_ldc(N);
+    r.setup = align256((size_t)r.m * r.ldc * 2);
+    r.total = r.setup + wy_ws(s, n, sym, true).total;
+    return r;
+}
+
 // Launchers defined in hh_wy.hip.
 // Setup: normalised reflectors, T; with lam also the padded spectrum and,
 // when want_m, the fragments of Y^T diag(lam) Y (streaming symmetric form).

@@ -13,8 +13,9 @@ compact-WY matrix-core kernels (data in that dtype, parameters in float32).
 ``algo`` may force "fused" or "wy"; the default "auto" follows ``compute``.
 
 On the WY path a forward whose reflectors (or spectrum) need a gradient keeps
-the per-vector WY coefficients (h scalars per vector, not h copies of the
-vector), and its backward uses them instead of a second pass over X.
+a record of its per-vector WY coefficients (h scalars per vector, not h copies
+of the vector) and of its reflector setup; its backward uses them instead of a
+second pass over X and a second setup.
 """
 from __future__ import annotations
 
@@ -76,14 +77,14 @@ def apply_raw(U, X, trans=False, compute=None, algo="auto", out=None, save=False
     desc = L.make_desc(n, h, N, param, io, comp, algo)
     Y = torch.empty((N, n), dtype=io, device=X.device) if out is None else out
     op = L.HH_OP_APPLY_T if trans else L.HH_OP_APPLY
-    ws = L.workspace(op, desc, X.device)
     ldu = max(n, U.stride(0) if h else n)
-    if save:
+    if save:  # the record takes the place of the workspace
         rec = L.saved_record(op, desc, X.device)
         L.check("hh_forward_save", L.lib().hh_forward_save(
             op, ctypes.byref(desc), L.ptr(U), ldu, None, L.ptr(X), L.ld(X), L.ptr(Y), L.ld(Y),
-            L.ptr(rec), rec.numel(), L.ptr(ws), ws.numel(), L.stream_of(X)))
+            L.ptr(rec), rec.numel(), None, 0, L.stream_of(X)))
         return Y, rec
+    ws = L.workspace(op, desc, X.device)
     fn = L.lib().hh_apply_T if trans else L.lib().hh_apply
     L.check("hh_apply_T" if trans else "hh_apply",
             fn(ctypes.byref(desc), L.ptr(U), ldu, L.ptr(X), L.ld(X),
@@ -101,14 +102,14 @@ def sym_raw(U, lam, X, compute=None, algo="auto", out=None, save=False):
     h = U.shape[0]
     desc = L.make_desc(n, h, N, param, io, comp, algo)
     Y = torch.empty((N, n), dtype=io, device=X.device) if out is None else out
-    ws = L.workspace(L.HH_OP_SYM, desc, X.device)
     ldu = max(n, U.stride(0) if h else n)
-    if save:
+    if save:  # the record takes the place of the workspace
         rec = L.saved_record(L.HH_OP_SYM, desc, X.device)
         L.check("hh_forward_save", L.lib().hh_forward_save(
             L.HH_OP_SYM, ctypes.byref(desc), L.ptr(U), ldu, L.ptr(lam), L.ptr(X), L.ld(X),
-            L.ptr(Y), L.ld(Y), L.ptr(rec), rec.numel(), L.ptr(ws), ws.numel(), L.stream_of(X)))
+            L.ptr(Y), L.ld(Y), L.ptr(rec), rec.numel(), None, 0, L.stream_of(X)))
         return Y, rec
+    ws = L.workspace(L.HH_OP_SYM, desc, X.device)
     L.check("hh_sym_apply", L.lib().hh_sym_apply(
         ctypes.byref(desc), L.ptr(U), ldu, L.ptr(lam), L.ptr(X),
         L.ld(X), L.ptr(Y), L.ld(Y), L.ptr(ws), ws.numel(), L.stream_of(X)))

@@ -126,7 +126,14 @@ def test_saved_size():
                              (1024, 64, 0, L.HH_OP_APPLY, 64)]:
         d = _wy_desc(n, h, N)
         assert lib.hh_saved_size(op, ctypes.byref(d), ctypes.byref(nb)) == L.HH_OK
-        assert nb.value == m * max(32, (N + 31) // 32 * 32) * 2
+        # coefficient rows first, then the setup (256-byte aligned parts)
+        coef = m * max(32, (N + 31) // 32 * 32) * 2
+        assert nb.value > coef and nb.value % 256 == 0
+        d2 = _wy_desc(n, h, N + 64)
+        nb2 = ctypes.c_size_t(0)
+        lib.hh_saved_size(op, ctypes.byref(d2), ctypes.byref(nb2))
+        coef2 = m * ((N + 64 + 31) // 32 * 32) * 2
+        assert nb2.value - nb.value == -(-coef2 // 256) * 256 - (-(-coef // 256) * 256)
     d = _wy_desc()
     assert lib.hh_saved_size(L.HH_OP_MAHAL, ctypes.byref(d), ctypes.byref(nb)) == L.HH_ERR_INVALID_ARG
     assert lib.hh_saved_size(L.HH_OP_APPLY_BWD, ctypes.byref(d), ctypes.byref(nb)) == L.HH_ERR_INVALID_ARG

@@ -286,8 +286,8 @@ def test_wy_saved_record(dname, n, h, N, kind):
     # writing the record leaves the forward's output unchanged, bit for bit
     assert torch.equal(Y, Y0)
     ldc = max(32, (N + 31) // 32 * 32)
-    assert rec.numel() == m * ldc * 2
-    cols = rec.view(torch.int16).view(m, ldc)
+    assert rec.numel() > m * ldc * 2
+    cols = rec[:m * ldc * 2].view(torch.int16).view(m, ldc)
     assert torch.count_nonzero(cols[:, N:]) == 0
     # dX comes from the pass over dY alone
     assert torch.equal(dX, dX0)
@@ -304,10 +304,13 @@ def test_wy_saved_record_empty_batch():
     n = 256
     U, _ = make(n, 6, 1, dt)
     E = torch.empty((0, n), dtype=dt, device=dev())
+    # a freed, non-zero block that the record is likely to reuse
+    rec0 = torch.full((1 << 16,), 7, dtype=torch.uint8, device=dev())
+    del rec0
     Y, rec = P.apply_raw(U, E, compute=dt, save=True)
     torch.cuda.synchronize()
-    assert Y.shape == (0, n) and rec.numel() == 64 * 32 * 2
-    assert torch.count_nonzero(rec) == 0
+    assert Y.shape == (0, n) and rec.numel() > 64 * 32 * 2
+    assert torch.count_nonzero(rec[:64 * 32 * 2]) == 0
     dX, dU = P.apply_bwd_raw(U, E, E, compute=dt, saved=rec)
     torch.cuda.synchronize()
     assert torch.count_nonzero(dU) == 0
