@@ -329,3 +329,20 @@ def test_wy_autograd_uses_record():
     (Y.float() * G.float()).sum().backward()
     _, rdU = oracle.apply_bwd(host(U), host(X), host(G))
     assert rel_fro(host(U.grad), rdU) < TOL16
+
+
+@pytest.mark.parametrize("n,h,N", [(256, 12, 40), (8192, 64, 37)])  # resident / streaming kernel
+def test_wy_saved_record_in_place(n, h, N):
+    """A forward that keeps its record may overwrite its input (Y = X); the
+    backward, given the original X, matches the plain backward."""
+    dt = torch.bfloat16
+    U, X = make(n, h, N, dt, seed=31)
+    G = torch.randn((N, n), device=dev()).to(dt)
+    Xi = X.clone()
+    _, rec = P.apply_raw(U, Xi, compute=dt, out=Xi, save=True)
+    ref = oracle.apply(host(U), host(X))
+    assert rel_rows(host(Xi), ref) < TOL16
+    dX, dU = P.apply_bwd_raw(U, X, G, compute=dt, saved=rec)
+    rdX, rdU = oracle.apply_bwd(host(U), host(X), host(G))
+    assert rel_rows(host(dX), rdX) < TOL16
+    assert rel_fro(host(dU), rdU) < TOL16
