@@ -41,7 +41,7 @@ def make(n, h, N, dt, seed=0):
 # tails included); smaller shapes the register-resident one.
 SHAPES = [(4096, 64, 1000), (256, 10, 33), (512, 9, 100), (1024, 64, 50), (2048, 100, 40),
           (8192, 128, 20), (4096, 1, 17), (1000, 7, 31), (64, 3, 5), (8192, 64, 300),
-          (4096, 100, 129), (6144, 128, 257)]
+          (4096, 100, 129), (6144, 128, 257), (64, 100, 9), (32, 64, 40)]  # last two: h > n
 
 
 @pytest.mark.parametrize("dname", ["bf16", "f16"])

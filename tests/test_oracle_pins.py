@@ -191,6 +191,36 @@ def test_qr_matches_lapack_up_to_signs():
         assert np.all(V[k, :k] == 0.0)
 
 
+@pytest.mark.parametrize("n,h", [(6, 2), (12, 5), (40, 17), (64, 40)])
+def test_result3_partial_qr_block_structure(n, h):
+    """Result 3 at h < n - 1 (eqs. ReflectorStructure and theU2): the first h
+    QR reflectors of an orthonormal U bring it to the block form
+    [D_top 0; 0 U~] with D_top a +-1 diagonal and U~ orthonormal, and with
+    D = diag(D_top, sign(diag U~)) the error of U ~ J_1 ... J_h D is
+    ||U - J_1 ... J_h D||_F^2 = 2(n - h) - 2 sum_i |U~_ii|.  (Eq.
+    ReflectorStructure shows I_h in the top block: its reflectors are taken
+    with the sign that makes R's diagonal positive; with the textbook sign
+    choice v = x + sign(x_1)||x|| e_1 used here the top block carries R's
+    signs, which D absorbs.)"""
+    U0 = random_orthonormal(n, 100 + n + h)
+    V, _ = oracle.householder_qr(U0)
+    Vh = V[:h]
+    B = oracle.apply(Vh, U0.T, trans=True).T   # column c: J_h ... J_1 U0[:, c]
+    top = np.diag(B)[:h]
+    assert np.abs(np.abs(top) - 1).max() < 1e-13
+    assert np.abs(B[:h, :h] - np.diag(top)).max() < 1e-13
+    assert np.abs(B[:h, h:]).max() < 1e-13 and np.abs(B[h:, :h]).max() < 1e-13
+    Ut = B[h:, h:]
+    assert np.abs(Ut.T @ Ut - np.eye(n - h)).max() < 1e-13
+    D = np.concatenate([top, np.sign(np.diag(Ut))])
+    err = np.linalg.norm(U0 - oracle.dense_Q(Vh) * D[None, :]) ** 2
+    assert abs(err - (2 * (n - h) - 2 * np.abs(np.diag(Ut)).sum())) < 1e-11
+    # the reflectors taken in the other order do not give the block form
+    if h >= 2:
+        Br = oracle.apply(Vh[::-1], U0.T, trans=True).T
+        assert np.abs(Br[h:, :h]).max() > 1e-3
+
+
 def _known_Q(n, seed):
     """Reflectors whose product is a known orthonormal matrix (Result 3)."""
     U0 = random_orthonormal(n, seed)
