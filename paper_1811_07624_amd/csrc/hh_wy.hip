@@ -47,35 +47,52 @@ constexpr int kThreadsWY = kWaves * kWave;
 
 // ---------------------------------------------------------------------------
 // Setup kernels (FP64).
+// One block of kNormThreads per reflector k: u_k / ||u_k|| in FP64, rounded to
+// the 16-bit type and written to the three fragment-ordered copies, with
+// ||y_k||^2 of the rounded vector.  Sums: wave shuffles, then the wave
+// partials in a fixed order.
+constexpr int kNormThreads = 256;
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double block_sum_f64(double v, double *red) {
+    constexpr int NW = kNormThreads / kWave;
+    v = wave_sum_f64(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
 template <typename E>
-__global__ __launch_bounds__(256) void k_wy_norm(const float *__restrict__ U, int64_t ldu, int n,
-                                                int h, int npad, int hp,
-                                                typename E::elem *__restrict__ Yc,
-                                                typename E::elem *__restrict__ Yr,
-                                                typename E::elem *__restrict__ Ycs,
-                                                double *__restrict__ nrm2,
-                                                double *__restrict__ nrm_raw,
-                                                double *__restrict__ uh64) {
+__global__ __launch_bounds__(kNormThreads) void k_wy_norm(const float *__restrict__ U, int64_t ldu, int n,
+                                                         int h, int npad, int hp,
+                                                         typename E::elem *__restrict__ Yc,
+                                                         typename E::elem *__restrict__ Yr,
+                                                         typename E::elem *__restrict__ Ycs,
+                                                         double *__restrict__ nrm2,
+                                                         double *__restrict__ nrm_raw,
+                                                         double *__restrict__ uh64) {
     using el = typename E::elem;
-    __shared__ double red[256];
+    __shared__ double red[kNormThreads / kWave];
     const int k = blockIdx.x;
     const int t = threadIdx.x;
     double s = 0.0;
     if (k < h)
-        for (int i = t; i < n; i += 256) {
+        for (int i = t; i < n; i += kNormThreads) {
             const double v = (double)U[(int64_t)k * ldu + i];
             s += v * v;
         }
-    red[t] = s;
-    __syncthreads();
-    for (int q = 128; q > 0; q >>= 1) {
-        if (t < q) red[t] += red[t + q];
-        __syncthreads();
-    }
-    const double r = sqrt(red[0]);
-    __syncthreads();
+    const double r = sqrt(block_sum_f64(s, red));
     double s2 = 0.0;
-    for (int i = t; i < npad; i += 256) {
+    for (int i = t; i < npad; i += kNormThreads) {
         double v = 0.0;
         if (k < h && i < n && r > 0.0) v = (double)U[(int64_t)k * ldu + i] / r;
         const el y = (el)v;
@@ -86,14 +103,9 @@ __global__ __launch_bounds__(256) void k_wy_norm(const float *__restrict__ U, in
         const double yd = (double)y;
         s2 += yd * yd;
     }
-    red[t] = s2;
-    __syncthreads();
-    for (int q = 128; q > 0; q >>= 1) {
-        if (t < q) red[t] += red[t + q];
-        __syncthreads();
-    }
+    s2 = block_sum_f64(s2, red);
     if (t == 0) {
-        nrm2[k] = red[0];
+        nrm2[k] = s2;
         if (nrm_raw) nrm_raw[k] = (k < h) ? r : 0.0;
     }
 }
@@ -155,23 +167,37 @@ __global__ __launch_bounds__(256) void k_wy_gram(const typename E::elem *__restr
 // inversion in LDS: the 16 x 16 diagonal blocks are inverted by back
 // substitution (one column per thread), then neighbouring inverted blocks of
 // [A B; 0 C] are merged, the off-diagonal block becoming -A^{-1} (B C^{-1}),
-// doubling the block size at each level (each thread forms a 4 x 4 piece).
-// Tm = T as FP32, row-major; Tw = T in FP64 (zero below the diagonal).
-__global__ __launch_bounds__(256) void k_wy_tmat(const double *__restrict__ G,
-                                                const double *__restrict__ nrm2, int hp,
-                                                double *__restrict__ Tw, float *__restrict__ Tm) {
+// doubling the block size at each level (each thread forms a 2 x 2 piece;
+// every element is accumulated in the same order whatever the thread count).
+// Outputs: Tm = T as FP32, row-major; Tw = T in FP64 (zero below the
+// diagonal); Tf = T (tr = 0) and T^T (tr = 1) as 16-bit MFMA A-operand
+// fragments split into hi + lo parts (hi = T rounded, lo = the rest rounded)
+// for the streaming kernel's T product: fragment (tr, hl, ib, kb), lane (c, g),
+// element j holds T'[sigma_row(ib, c)][32 kb + 8 g + j].
+constexpr int kTmatThreads = 1024;
+
+template <int HP, typename E>
+__global__ __launch_bounds__(kTmatThreads) void k_wy_tmat(const double *__restrict__ G,
+                                                         const double *__restrict__ nrm2,
+                                                         double *__restrict__ Tw, float *__restrict__ Tm,
+                                                         typename E::elem *__restrict__ Tf) {
+    using el = typename E::elem;
+    constexpr int LD = HP + 1, NT = kTmatThreads;
     extern __shared__ double M[];
-    const int LD = hp + 1;
     const int t = threadIdx.x;
-#pragma unroll 8
-    for (int idx = t; idx < hp * hp; idx += 256) {
-        const int i = idx / hp, k = idx % hp;
-        const double g = G[idx];
-        M[i * LD + k] = k > i ? g : k < i ? 0.0 : (nrm2[i] > 0.0 ? 0.5 * nrm2[i] : 0.5);
+#pragma unroll
+    for (int r = 0; r < (HP * HP + NT - 1) / NT; ++r) {
+        const int idx = t + r * NT;
+        if (idx < HP * HP) {
+            const int i = idx / HP, k = idx % HP;
+            const double g = G[idx];
+            const double d = nrm2[i];
+            M[i * LD + k] = k > i ? g : k < i ? 0.0 : (d > 0.0 ? 0.5 * d : 0.5);
+        }
     }
     __syncthreads();
     {
-        const bool act = t < hp;  // hp / 16 blocks x 16 columns
+        const bool act = t < HP;  // HP / 16 blocks x 16 columns
         const int o = 16 * (t >> 4), jc = t & 15;
         double x[16];
         if (act) {
@@ -190,74 +216,74 @@ __global__ __launch_bounds__(256) void k_wy_tmat(const double *__restrict__ G,
         }
         __syncthreads();
     }
-    for (int s = 16; s < hp; s *= 2) {
-        const int tq = s / 4;
-        const bool act = t < (hp / (2 * s)) * tq * tq;
-        const int pidx = t / (tq * tq), rr = t % (tq * tq);
-        const int i0 = 2 * s * pidx, a0 = i0 + 4 * (rr / tq), b0 = i0 + s + 4 * (rr % tq);
-        double acc[4][4];
+#pragma unroll
+    for (int s = 16; s < HP; s *= 2) {
+        const int th = s / 2;  // 2 x 2 pieces per row of an s x s block
+        const bool act = t < (HP / (2 * s)) * th * th;
+        const int pidx = t / (th * th), rr = t % (th * th);
+        const int i0 = 2 * s * pidx, a0 = i0 + 2 * (rr / th), b0 = i0 + s + 2 * (rr % th);
+        double acc[2][2];
         for (int step = 0; step < 2; ++step) {
             if (act) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < 2; ++q)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[q][r] = 0.0;
+                    for (int r = 0; r < 2; ++r) acc[q][r] = 0.0;
                 // step 0: B C^{-1} (C^{-1} at rows/cols i0+s..); step 1: A^{-1} X (X in B's place)
                 const int ka = step == 0 ? i0 + s : i0;
-#pragma unroll 4
-                for (int c = 0; c < s; ++c) {  // s is a multiple of 16
-                    double av[4], bv[4];
+#pragma unroll 8
+                for (int c = 0; c < s; ++c) {
+                    double av[2], bv[2];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
+                    for (int q = 0; q < 2; ++q) {
                         av[q] = M[(a0 + q) * LD + ka + c];
                         bv[q] = M[(ka + c) * LD + b0 + q];
                     }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
+                    for (int q = 0; q < 2; ++q)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) acc[q][r] += av[q] * bv[r];
+                        for (int r = 0; r < 2; ++r) acc[q][r] += av[q] * bv[r];
                 }
             }
             __syncthreads();
             if (act) {
                 const double sg = step == 0 ? 1.0 : -1.0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < 2; ++q)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) M[(a0 + q) * LD + b0 + r] = sg * acc[q][r];
+                    for (int r = 0; r < 2; ++r) M[(a0 + q) * LD + b0 + r] = sg * acc[q][r];
             }
             __syncthreads();
         }
     }
-    for (int idx = t; idx < hp * hp; idx += 256) {
-        const int i = idx / hp, k = idx % hp;
-        const double v = (k >= i) ? M[i * LD + k] : 0.0;
-        Tw[idx] = v;
-        Tm[idx] = (float)v;
-    }
-}
-
-// T (tr = 0) and T^T (tr = 1) as 16-bit MFMA A-operand fragments split into
-// hi + lo parts (hi = T rounded, lo = the rest rounded), for the streaming
-// kernel's T product.  Fragment (tr, hl, ib, kb), lane (c, g), element j holds
-// T'[sigma_row(ib, c)][32 kb + 8 g + j].  One thread per (fragment, lane).
-template <typename E>
-__global__ __launch_bounds__(256) void k_wy_tfrag(const double *__restrict__ Tw, int hp,
-                                                 typename E::elem *__restrict__ Tf) {
-    using el = typename E::elem;
-    const int HB = hp >> 4, KS = hp >> 5;
-    const int id = blockIdx.x * 256 + threadIdx.x;
-    if (id >= 4 * HB * KS * 64) return;
-    const int lane = id & 63, f = id >> 6;
-    const int kb = f % KS, ib = (f / KS) % HB, hl = (f / (KS * HB)) & 1, tr = f / (2 * KS * HB);
-    const int c = lane & 15, g = lane >> 4;
-    const int r = sigma_row(ib, c);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int col = 32 * kb + 8 * g + j;
-        const double t = tr ? Tw[col * hp + r] : Tw[r * hp + col];
-        const el hi = (el)t;
-        Tf[(size_t)id * 8 + j] = hl ? (el)(t - (double)hi) : hi;
+    for (int r = 0; r < (HP * HP + NT - 1) / NT; ++r) {
+        const int idx = t + r * NT;
+        if (idx < HP * HP) {
+            const int i = idx / HP, k = idx % HP;
+            const double v = (k >= i) ? M[i * LD + k] : 0.0;
+            Tw[idx] = v;
+            Tm[idx] = (float)v;
+        }
+    }
+    // fragments (the lower triangle of M is zero)
+    constexpr int HB = HP / 16, KS = HP / 32, NF = 4 * HB * KS * 64;
+    for (int id = t; id < NF; id += NT) {
+        const int lane = id & 63, f = id >> 6;
+        const int kb = f % KS, ib = (f / KS) % HB, hl = (f / (KS * HB)) & 1, tr = f / (2 * KS * HB);
+        const int c = lane & 15, g = lane >> 4;
+        const int row = sigma_row(ib, c);
+        typename E::vec8 fr;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int col = 32 * kb + 8 * g + j;
+            const double v = tr ? M[col * LD + row] : M[row * LD + col];
+            // through FP32: hi may differ from T's direct 16-bit rounding in a
+            // tie, and lo = T - hi (formed in FP64) absorbs that
+            const el hi = (el)(float)v;
+            fr[j] = hl ? (el)(float)(v - (double)hi) : hi;
+        }
+        *reinterpret_cast<typename E::vec8 *>(Tf + (size_t)id * 8) = fr;
     }
 }
 
@@ -576,7 +602,7 @@ hipError_t wy_setup(const WyShape &s, const float *U, int64_t ldu, int64_t n, in
     if (lam)
         hipLaunchKernelGGL(k_fill_lam, dim3((s.npad + 255) / 256), dim3(256), 0, st, lam, (int)n, s.npad,
                            reinterpret_cast<float *>(ws + w.lam));
-    hipLaunchKernelGGL((k_wy_norm<E>), dim3(hp), dim3(256), 0, st, U, ldu, (int)n, (int)h, s.npad,
+    hipLaunchKernelGGL((k_wy_norm<E>), dim3(hp), dim3(kNormThreads), 0, st, U, ldu, (int)n, (int)h, s.npad,
                        hp, reinterpret_cast<el *>(ws + w.yc), reinterpret_cast<el *>(ws + w.yr),
                        reinterpret_cast<el *>(ws + w.ycs),
                        reinterpret_cast<double *>(ws + w.nrm2),
@@ -591,13 +617,19 @@ hipError_t wy_setup(const WyShape &s, const float *U, int64_t ldu, int64_t n, in
                        m ? gp + kGramSeg * hh : nullptr);
     hipLaunchKernelGGL((k_sum_parts<double>), dim3(hp * hp / 32, m ? 2 : 1), dim3(256), 0, st, gp, kGramSeg,
                        hh, hp * hp, reinterpret_cast<double *>(ws + w.gsum));
-    hipLaunchKernelGGL(k_wy_tmat, dim3(1), dim3(256), (size_t)hp * (hp + 1) * 8, st,
-                       reinterpret_cast<const double *>(ws + w.gsum),
-                       reinterpret_cast<const double *>(ws + w.nrm2), hp,
-                       reinterpret_cast<double *>(ws + w.tw), reinterpret_cast<float *>(ws + w.tm));
+    {
+        const double *gs = reinterpret_cast<const double *>(ws + w.gsum);
+        const double *n2 = reinterpret_cast<const double *>(ws + w.nrm2);
+        double *tw = reinterpret_cast<double *>(ws + w.tw);
+        float *tm = reinterpret_cast<float *>(ws + w.tm);
+        el *tf = reinterpret_cast<el *>(ws + w.tf);
+        const size_t lds = (size_t)hp * (hp + 1) * 8;
+        if (hp == 64)
+            hipLaunchKernelGGL((k_wy_tmat<64, E>), dim3(1), dim3(kTmatThreads), lds, st, gs, n2, tw, tm, tf);
+        else
+            hipLaunchKernelGGL((k_wy_tmat<128, E>), dim3(1), dim3(kTmatThreads), lds, st, gs, n2, tw, tm, tf);
+    }
     const int nfrag = 4 * (hp / 16) * (hp / 32) * 64;
-    hipLaunchKernelGGL((k_wy_tfrag<E>), dim3((nfrag + 255) / 256), dim3(256), 0, st,
-                       reinterpret_cast<const double *>(ws + w.tw), hp, reinterpret_cast<el *>(ws + w.tf));
     if (m)
         hipLaunchKernelGGL((k_wy_mfrag<E>), dim3((nfrag / 2 + 255) / 256), dim3(256), 0, st,
                            reinterpret_cast<const double *>(ws + w.gsum) + hh, hp,
