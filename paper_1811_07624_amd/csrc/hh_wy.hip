@@ -326,11 +326,9 @@ __global__ __launch_bounds__(kThreadsWY, 2 * MINB) void k_wy_fwd(WyArgs a) {
     // LDS row strides are padded so that the lanes of one access fall in
     // different banks.
     constexpr int NBP = NB + 4;   // partial sums row stride
-    constexpr int HTP = HP + 1;   // T row stride
     constexpr int HBP = HP + 8;   // W' fragment row stride (keeps 16-byte alignment)
     float *sP = reinterpret_cast<float *>(smem);                  // [kWaves][HP][NBP]
-    float *sT = sP + kWaves * HP * NBP;                           // [HP][HTP]
-    el *sB = reinterpret_cast<el *>(sT + ((HP * HTP + 3) & ~3));  // [2][CB][16][HBP]
+    el *sB = reinterpret_cast<el *>(sP + kWaves * HP * NBP);      // [2][CB][16][HBP]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -341,11 +339,10 @@ __global__ __launch_bounds__(kThreadsWY, 2 * MINB) void k_wy_fwd(WyArgs a) {
     const int n = a.n, npad = a.npad;
     const __amdgpu_buffer_rsrc_t rYc = make_rsrc(a.Yc, (uint32_t)HP * npad * 2);
     const __amdgpu_buffer_rsrc_t rYr = make_rsrc(a.Yr, (uint32_t)HP * npad * 2);
+    const __amdgpu_buffer_rsrc_t rTf = make_rsrc(a.Tf, (uint32_t)(8 * HP * HP));
     const el *X = static_cast<const el *>(a.X);
     el *Yo = static_cast<el *>(a.Y);
 
-    for (int i = tid; i < HP * HP; i += kThreadsWY) sT[(i / HP) * HTP + i % HP] = a.Tm[i];
-    __syncthreads();
 
     // lane parts of the buffer offsets (bytes) into the fragment-ordered
     // reflector copies; the (hb, p, m, ks) parts are uniform
@@ -389,6 +386,24 @@ __global__ __launch_bounds__(kThreadsWY, 2 * MINB) void k_wy_fwd(WyArgs a) {
                 for (int cb = 0; cb < CB; ++cb) acc[hb][cb] = E::mfma(av[hb], xr[p][cb], acc[hb][cb]);
             __builtin_amdgcn_sched_barrier(0);
         }
+        // The T product runs on the matrix cores: wave w < HB * CB forms the
+        // 16-row block ib of W' for the 16 vectors of column block cb, from T
+        // (or T^T) as 16-bit hi + lo fragments (rows permuted by sigma_row)
+        // and W as hi + lo parts (three products, lo * lo dropped).  Its T
+        // fragments are fetched now (from L2; no HBM access is outstanding) so
+        // that they arrive while the partial sums are formed.
+        constexpr int NPAIR = HB * CB;
+        const bool tw = w < NPAIR;
+        const int ibw = w % HB, cbw = w / HB;
+        const int trn = trans ? 1 : 0;
+        v8 th[KS], tl[KS];
+        if (tw) {
+#pragma unroll
+            for (int kb = 0; kb < KS; ++kb) {
+                th[kb] = bload<v8>(rTf, lane * 16, (((trn * 2 + 0) * HB + ibw) * KS + kb) * 1024);
+                tl[kb] = bload<v8>(rTf, lane * 16, (((trn * 2 + 1) * HB + ibw) * KS + kb) * 1024);
+            }
+        }
         // partials to LDS: element (h, col) of wave w
 #pragma unroll
         for (int hb = 0; hb < HB; ++hb)
@@ -409,33 +424,40 @@ __global__ __launch_bounds__(kThreadsWY, 2 * MINB) void k_wy_fwd(WyArgs a) {
         __syncthreads();
         // W' = T W  (or T^T W), split into 16-bit hi + lo, stored as the GEMM2
         // B operand: sB[hl][cb][c][h]
-        {
-            constexpr int TPR = NB / 4;                 // threads per row of W'
-            constexpr int RPP = kThreadsWY / TPR;       // rows per pass
-            const int c4 = (tid % TPR) * 4;
-            for (int i = tid / TPR; i < HP; i += RPP) {
-                // T is triangular; the zero half is multiplied too, which
-                // keeps the trip count fixed so the LDS reads pipeline.
-                f32x4 s = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 16
-                for (int k = 0; k < HP; ++k) {
-                    const float t = trans ? sT[k * HTP + i] : sT[i * HTP + k];
-                    const f32x4 wv = *reinterpret_cast<const f32x4 *>(sP + k * NBP + c4);
-                    s += t * wv;
-                }
+        if (tw) {
+            f32x4 zz = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int col = c4 + q;
-                    const el hi = (el)s[q];
-                    const el lo = (el)(s[q] - (float)hi);
-                    sB[((0 * CB + col / 16) * 16 + col % 16) * HBP + i] = hi;
-                    sB[((1 * CB + col / 16) * 16 + col % 16) * HBP + i] = lo;
-                }
-                if (a.coef) {  // coefficients for the backward pass, 16-bit
-                    el *cp = static_cast<el *>(a.coef) + (int64_t)(pass * HP + i) * a.ldc + col0 + c4;
+            for (int kb = 0; kb < KS; ++kb) {
+                v8 wh, wl;  // B operand: W[32 kb + 8 g + j][16 cb + c]
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (col0 + c4 + q < a.N) cp[q] = (el)s[q];
+                for (int j = 0; j < 8; ++j) {
+                    const float v = sP[(32 * kb + 8 * g + j) * NBP + 16 * cbw + c];
+                    const el hi = (el)v;
+                    wh[j] = hi;
+                    wl[j] = (el)(v - (float)hi);
+                }
+                zz = E::mfma(th[kb], wh, zz);
+                zz = E::mfma(th[kb], wl, zz);
+                zz = E::mfma(tl[kb], wh, zz);
+            }
+            // zz[i] is W'[sigma_row(ib, 4 g + i)][16 cb + c]: four consecutive rows
+            typedef el el4 __attribute__((ext_vector_type(4)));
+            const int r0 = sigma_row(ibw, 4 * g);
+            el4 h4, l4;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const el hi = (el)zz[i];
+                h4[i] = hi;
+                l4[i] = (el)(zz[i] - (float)hi);
+            }
+            *reinterpret_cast<el4 *>(sB + ((0 * CB + cbw) * 16 + c) * HBP + r0) = h4;
+            *reinterpret_cast<el4 *>(sB + ((1 * CB + cbw) * 16 + c) * HBP + r0) = l4;
+            if (a.coef) {  // coefficients for the backward pass, 16-bit
+                const int64_t col = col0 + 16 * cbw + c;
+                if (col < a.N) {
+                    el *cp = static_cast<el *>(a.coef) + (int64_t)(pass * HP + r0) * a.ldc + col;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) cp[(int64_t)i * a.ldc] = (el)zz[i];
                 }
             }
         }
@@ -583,8 +605,7 @@ __global__ __launch_bounds__(kThreadsWY, 2 * MINB) void k_wy_fwd(WyArgs a) {
 // Host side.
 size_t wy_lds_bytes(const WyShape &s) {
     const size_t nb = 16 * s.cb, hp = s.hp;
-    return kWaves * hp * (nb + 4) * 4 + ((hp * (hp + 1) + 3) & ~size_t(3)) * 4 +
-           2 * nb * (hp + 8) * 2;
+    return kWaves * hp * (nb + 4) * 4 + 2 * nb * (hp + 8) * 2;
 }
 
 __global__ void k_fill_lam(const float *__restrict__ lam, int n, int npad, float *__restrict__ out) {
