@@ -123,7 +123,7 @@ def test_strided_and_in_place(dtype):
     assert rel_rows(host(Xi), ref) < TOL[dtype]
 
 
-def test_config1_fp64_full():
+def test_qx_n64_h4_fp64_full():
     """n=64, h=4, N=1024 FP64, both Q X and Q^T X: relative error <= 1e-12."""
     U, X = make(64, 4, 1024, torch.float64, seed=0)
     for trans in (False, True):
