@@ -41,8 +41,11 @@
  * and data of that same type.  The WY algorithm (compact form Q = I - Y T Y^T,
  * prior art of Bischof & Van Loan and Schreiber & Van Loan, not the paper)
  * computes in BF16 or F16 on the matrix cores with FP32 accumulation, F32
- * parameters, and data in the compute type (BF16 or F16; F32 data is not
- * converted on load and returns HH_ERR_UNSUPPORTED).  HH_ALGO_AUTO picks
+ * parameters, and data in the compute type or in F32 (F32 data is rounded to
+ * the compute type, nearest even, into the workspace before the 16-bit kernels
+ * run and their 16-bit results are widened back: the results are those of the
+ * 16-bit path on the rounded data, at the cost of one extra pass over each
+ * F32 operand; hh_workspace_size then grows with N).  HH_ALGO_AUTO picks
  * FUSED for F64/F32 compute and WY for BF16/F16 compute.  Any other
  * combination returns HH_ERR_UNSUPPORTED.
  *
@@ -193,8 +196,9 @@ HH_API hh_status hh_saved_size(hh_op op, const hh_desc *d, size_t *bytes);
  * HH_OP_SYM only, else ignored) with the same Y as hh_apply / hh_apply_T /
  * hh_sym_apply, which also fills the record `saved` (device, non-null,
  * 16-byte aligned, saved_bytes >= hh_saved_size).  The record takes the place
- * of the workspace: ws may be null and ws_bytes 0.  With N == 0 only the setup
- * is recorded. */
+ * of the workspace: with data in the compute type ws may be null and ws_bytes
+ * 0; F32 data still needs hh_workspace_size(op) bytes for its conversion.
+ * With N == 0 only the setup is recorded. */
 HH_API hh_status hh_forward_save(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
                           const void *lam, const void *X, int64_t ldx, void *Y,
                           int64_t ldy, void *saved, size_t saved_bytes, void *ws,

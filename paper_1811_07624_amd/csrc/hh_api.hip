@@ -82,9 +82,9 @@ static hh_status check_desc(const hh_desc *d, Algo *algo) {
     }
     if (a == HH_ALGO_WY) {
         if (!(d->compute_dtype == HH_BF16 || d->compute_dtype == HH_F16) ||
-            d->param_dtype != HH_F32 || d->io_dtype != d->compute_dtype)
+            d->param_dtype != HH_F32 || (d->io_dtype != d->compute_dtype && d->io_dtype != HH_F32))
             return fail(HH_ERR_UNSUPPORTED,
-                        "WY needs compute in {BF16, F16}, param F32 and io = compute");
+                        "WY needs compute in {BF16, F16}, param F32 and io = compute or F32");
         *algo = Algo::WY;
         return HH_OK;
     }

@@ -729,7 +729,7 @@ hipError_t wy_main_any(bool bf, const WyShape &s, WyOp op, const WyArgs &a, hipS
     return bf ? dispatch_main<BF16>(s, op, a, st) : dispatch_main<F16>(s, op, a, st);
 }
 
-hh_status wy_workspace_size(hh_op op, const hh_desc *d, size_t *bytes) {
+hh_status wy_workspace_size16(hh_op op, const hh_desc *d, size_t *bytes) {
     WyShape s;
     if (!wy_shape(d->n, d->h, &s))
         return set_error(HH_ERR_UNSUPPORTED, "WY path supports n <= 8192 and h <= 128");
@@ -753,7 +753,7 @@ hh_status wy_saved_size(hh_op op, const hh_desc *d, size_t *bytes) {
     return HH_OK;
 }
 
-hh_status wy_forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, const void *lam,
+hh_status wy_forward16(hh_op op, const hh_desc *d, const void *U, int64_t ldu, const void *lam,
                      const void *X, int64_t ldx, const void *Xb, int64_t ldb, void *Y,
                      int64_t ldy, void *saved, size_t saved_bytes, void *ws, size_t ws_bytes,
                      hipStream_t st) {

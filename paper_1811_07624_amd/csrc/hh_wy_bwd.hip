@@ -484,7 +484,7 @@ hipError_t wy_zero_pad(void *rows, int m, int64_t N, int64_t ldc, hipStream_t st
     return hipGetLastError();
 }
 
-hh_status wy_backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu, const void *lam,
+hh_status wy_backward16(hh_op op, const hh_desc *d, const void *U, int64_t ldu, const void *lam,
                       const void *X, int64_t ldx, const void *Xb, int64_t ldb, const void *G,
                       int64_t ldg, void *dX, void *dXb, int64_t lddx, void *dU, int64_t lddu,
                       void *dlam, const void *saved, size_t saved_bytes, void *ws,

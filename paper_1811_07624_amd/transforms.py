@@ -9,7 +9,8 @@ returns; no arithmetic on the data happens in Python.
 
 ``compute`` selects the arithmetic: float64/float32 run the fused
 sequential-reflector kernels (data in that dtype); bfloat16/float16 run the
-compact-WY matrix-core kernels (data in that dtype, parameters in float32).
+compact-WY matrix-core kernels (data in that dtype or in float32, which the
+library rounds to the compute type and widens back; parameters in float32).
 ``algo`` may force "fused" or "wy"; the default "auto" follows ``compute``.
 
 On the WY path a forward whose reflectors (or spectrum) need a gradient keeps
@@ -78,11 +79,12 @@ def apply_raw(U, X, trans=False, compute=None, algo="auto", out=None, save=False
     Y = torch.empty((N, n), dtype=io, device=X.device) if out is None else out
     op = L.HH_OP_APPLY_T if trans else L.HH_OP_APPLY
     ldu = max(n, U.stride(0) if h else n)
-    if save:  # the record takes the place of the workspace
+    if save:  # the record takes the place of the workspace (FP32 data: conversion space)
         rec = L.saved_record(op, desc, X.device)
+        ws = L.workspace(op, desc, X.device) if io != comp else None
         L.check("hh_forward_save", L.lib().hh_forward_save(
             op, ctypes.byref(desc), L.ptr(U), ldu, None, L.ptr(X), L.ld(X), L.ptr(Y), L.ld(Y),
-            L.ptr(rec), rec.numel(), None, 0, L.stream_of(X)))
+            L.ptr(rec), rec.numel(), L.ptr(ws), 0 if ws is None else ws.numel(), L.stream_of(X)))
         return Y, rec
     ws = L.workspace(op, desc, X.device)
     fn = L.lib().hh_apply_T if trans else L.lib().hh_apply
@@ -103,11 +105,13 @@ def sym_raw(U, lam, X, compute=None, algo="auto", out=None, save=False):
     desc = L.make_desc(n, h, N, param, io, comp, algo)
     Y = torch.empty((N, n), dtype=io, device=X.device) if out is None else out
     ldu = max(n, U.stride(0) if h else n)
-    if save:  # the record takes the place of the workspace
+    if save:  # the record takes the place of the workspace (FP32 data: conversion space)
         rec = L.saved_record(L.HH_OP_SYM, desc, X.device)
+        ws = L.workspace(L.HH_OP_SYM, desc, X.device) if io != comp else None
         L.check("hh_forward_save", L.lib().hh_forward_save(
             L.HH_OP_SYM, ctypes.byref(desc), L.ptr(U), ldu, L.ptr(lam), L.ptr(X), L.ld(X),
-            L.ptr(Y), L.ld(Y), L.ptr(rec), rec.numel(), None, 0, L.stream_of(X)))
+            L.ptr(Y), L.ld(Y), L.ptr(rec), rec.numel(), L.ptr(ws), 0 if ws is None else ws.numel(),
+            L.stream_of(X)))
         return Y, rec
     ws = L.workspace(L.HH_OP_SYM, desc, X.device)
     L.check("hh_sym_apply", L.lib().hh_sym_apply(

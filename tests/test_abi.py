@@ -69,9 +69,14 @@ def test_unsupported_combinations():
     assert _apply(_desc(p=L.HH_F64, io=L.HH_BF16, c=L.HH_BF16)) == L.HH_ERR_UNSUPPORTED
     # FUSED forced on a 16-bit compute type
     assert _apply(_desc(c=L.HH_BF16, algo=L.HH_ALGO_FUSED)) == L.HH_ERR_UNSUPPORTED
-    # WY reads and writes data in its 16-bit compute type only
-    assert _apply(_desc(n=64, h=4, p=L.HH_F32, io=L.HH_F32, c=L.HH_BF16)) == L.HH_ERR_UNSUPPORTED
+    # WY data: the compute type or F32 (converted), not the other 16-bit type
     assert _apply(_desc(n=64, h=4, p=L.HH_F32, io=L.HH_F16, c=L.HH_BF16)) == L.HH_ERR_UNSUPPORTED
+    # F32 data on WY: n must be a multiple of 8; a missing workspace is caught
+    # before anything is enqueued
+    assert _apply(_desc(n=60, h=4, p=L.HH_F32, io=L.HH_F32, c=L.HH_BF16), ldu=60, ldx=60,
+                  ldy=60) == L.HH_ERR_UNSUPPORTED
+    assert _apply(_desc(n=64, h=4, p=L.HH_F32, io=L.HH_F32, c=L.HH_BF16), ldu=64, ldx=64,
+                  ldy=64) == L.HH_ERR_INVALID_ARG
     # fused kernels cover n <= 8192 (FP32)
     assert _apply(_desc(n=8193), ldu=8193, ldx=8193, ldy=8193) == L.HH_ERR_UNSUPPORTED
 

@@ -346,3 +346,38 @@ def test_wy_saved_record_in_place(n, h, N):
     rdX, rdU = oracle.apply_bwd(host(U), host(X), host(G))
     assert rel_rows(host(dX), rdX) < TOL16
     assert rel_fro(host(dU), rdU) < TOL16
+
+
+# ----------------------------------------------------------------------------
+# FP32 data on the WY path: rounded to the compute type, widened back
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dname", ["bf16", "f16"])
+@pytest.mark.parametrize("n,h,N", [(512, 9, 100), (8192, 64, 37)])  # resident / streaming kernel
+def test_wy_fp32_data_equals_16bit_path(dname, n, h, N):
+    """FP32 data gives exactly the 16-bit path's results on the rounded data,
+    widened to FP32, forward and backward (with and without the saved record)."""
+    dt = DT[dname]
+    U, _ = make(n, h, N, dt, seed=41)
+    Xf = torch.tensor(synth.gaussian((N, n), seed=42), dtype=torch.float32, device=dev())
+    Gf = torch.tensor(synth.gaussian((N, n), seed=43, stream=synth.STREAM_G), dtype=torch.float32,
+                      device=dev())
+    lam = torch.tensor(synth.eig_loguniform(n, seed=5), dtype=torch.float32, device=dev())
+    X16, G16 = Xf.to(dt), Gf.to(dt)
+    for trans in (False, True):
+        Y = P.apply_raw(U, Xf, trans=trans, compute=dt)
+        assert Y.dtype == torch.float32
+        assert torch.equal(Y, P.apply_raw(U, X16, trans=trans, compute=dt).float())
+        dX, dU = P.apply_bwd_raw(U, Xf, Gf, trans=trans, compute=dt)
+        dX16, dU16 = P.apply_bwd_raw(U, X16, G16, trans=trans, compute=dt)
+        assert torch.equal(dX, dX16.float()) and torch.equal(dU, dU16)
+    Y, rec = P.sym_raw(U, lam, Xf, compute=dt, save=True)
+    Y16, rec16 = P.sym_raw(U, lam, X16, compute=dt, save=True)
+    m = 2 * (64 if h <= 64 else 128)
+    nb = m * max(32, (N + 31) // 32 * 32) * 2  # the coefficient rows of the record
+    assert torch.equal(Y, Y16.float()) and torch.equal(rec[:nb], rec16[:nb])
+    dX, dU, dl = P.sym_bwd_raw(U, lam, Xf, Gf, compute=dt, saved=rec)
+    dX16, dU16, dl16 = P.sym_bwd_raw(U, lam, X16, G16, compute=dt, saved=rec16)
+    assert torch.equal(dX, dX16.float()) and torch.equal(dU, dU16) and torch.equal(dl, dl16)
+    # and against the oracle on the FP32 data (rounding of X is path error here)
+    ref = oracle.sym(host(U), host(lam), host(Xf))
+    assert rel_rows(host(Y), ref) < TOL16
