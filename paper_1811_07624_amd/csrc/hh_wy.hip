@@ -169,8 +169,7 @@ __global__ __launch_bounds__(256) void k_wy_gram(const typename E::elem *__restr
 // [A B; 0 C] are merged, the off-diagonal block becoming -A^{-1} (B C^{-1}),
 // doubling the block size at each level (each thread forms a 2 x 2 piece;
 // every element is accumulated in the same order whatever the thread count).
-// Outputs: Tm = T as FP32, row-major; Tw = T in FP64 (zero below the
-// diagonal); Tf = T (tr = 0) and T^T (tr = 1) as 16-bit MFMA A-operand
+// Outputs: Tw = T in FP64 (zero below the diagonal); Tf = T (tr = 0) and T^T (tr = 1) as 16-bit MFMA A-operand
 // fragments split into hi + lo parts (hi = T rounded, lo = the rest rounded)
 // for the streaming kernel's T product: fragment (tr, hl, ib, kb), lane (c, g),
 // element j holds T'[sigma_row(ib, c)][32 kb + 8 g + j].
@@ -179,7 +178,7 @@ constexpr int kTmatThreads = 1024;
 template <int HP, typename E>
 __global__ __launch_bounds__(kTmatThreads) void k_wy_tmat(const double *__restrict__ G,
                                                          const double *__restrict__ nrm2,
-                                                         double *__restrict__ Tw, float *__restrict__ Tm,
+                                                         double *__restrict__ Tw,
                                                          typename E::elem *__restrict__ Tf) {
     using el = typename E::elem;
     constexpr int LD = HP + 1, NT = kTmatThreads;
@@ -263,7 +262,6 @@ __global__ __launch_bounds__(kTmatThreads) void k_wy_tmat(const double *__restri
             const int i = idx / HP, k = idx % HP;
             const double v = (k >= i) ? M[i * LD + k] : 0.0;
             Tw[idx] = v;
-            Tm[idx] = (float)v;
         }
     }
     // fragments (the lower triangle of M is zero)
@@ -642,13 +640,12 @@ hipError_t wy_setup(const WyShape &s, const float *U, int64_t ldu, int64_t n, in
         const double *gs = reinterpret_cast<const double *>(ws + w.gsum);
         const double *n2 = reinterpret_cast<const double *>(ws + w.nrm2);
         double *tw = reinterpret_cast<double *>(ws + w.tw);
-        float *tm = reinterpret_cast<float *>(ws + w.tm);
         el *tf = reinterpret_cast<el *>(ws + w.tf);
         const size_t lds = (size_t)hp * (hp + 1) * 8;
         if (hp == 64)
-            hipLaunchKernelGGL((k_wy_tmat<64, E>), dim3(1), dim3(kTmatThreads), lds, st, gs, n2, tw, tm, tf);
+            hipLaunchKernelGGL((k_wy_tmat<64, E>), dim3(1), dim3(kTmatThreads), lds, st, gs, n2, tw, tf);
         else
-            hipLaunchKernelGGL((k_wy_tmat<128, E>), dim3(1), dim3(kTmatThreads), lds, st, gs, n2, tw, tm, tf);
+            hipLaunchKernelGGL((k_wy_tmat<128, E>), dim3(1), dim3(kTmatThreads), lds, st, gs, n2, tw, tf);
     }
     const int nfrag = 4 * (hp / 16) * (hp / 32) * 64;
     if (m)
@@ -810,7 +807,6 @@ hh_status wy_forward16(hh_op op, const hh_desc *d, const void *U, int64_t ldu, c
     a.Ycs = base + w.ycs;
     a.Tf = base + w.tf;
     a.Mf = base + w.mf;
-    a.Tm = reinterpret_cast<const float *>(base + w.tm);
     a.lam = reinterpret_cast<const float *>(base + w.lam);
     a.store = 1;
     a.coef = saved;

@@ -534,7 +534,6 @@ hh_status wy_backward16(hh_op op, const hh_desc *d, const void *U, int64_t ldu, 
     a.Ycs = sb + L.base.ycs;
     a.Tf = sb + L.base.tf;
     a.Mf = sb + L.base.mf;
-    a.Tm = reinterpret_cast<const float *>(sb + L.base.tm);
     a.lam = reinterpret_cast<const float *>(sb + L.base.lam);
     a.ldc = L.ldc;
     a.n = (int)n;

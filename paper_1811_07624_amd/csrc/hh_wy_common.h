@@ -94,7 +94,6 @@ struct WyArgs {
     const void *Ycs;  // streaming kernel: GEMM1 operand, chunk-major (ycs_index)
     const void *Tf;   // streaming kernel: T and T^T as 16-bit hi/lo MFMA fragments
     const void *Mf;   // streaming kernel, SYM: Y^T diag(lam) Y as hi/lo fragments
-    const float *Tm;  // HP x HP row-major
     const float *lam; // npad (SYM)
     void *coef;       // nullable: W' of pass q written to rows [q*HP, (q+1)*HP), ld = ldc
     int64_t ldc;
@@ -130,7 +129,7 @@ inline int64_t wy_ldc(int64_t N) { return N <= 32 ? 32 : (N + 31) / 32 * 32; }
 // partials, gsum -> [2][hp][hp] (Y^T Y, then Y^T diag(lam) Y), and mf holds
 // the fragments of the second.
 struct WyWs {
-    size_t yc, yr, ycs, tf, mf, nrm2, nrmraw, gram, gsum, tw, tm, lam, uh64, total;
+    size_t yc, yr, ycs, tf, mf, nrm2, nrmraw, gram, gsum, tw, lam, uh64, total;
 };
 
 inline WyWs wy_ws(const WyShape &s, int64_t n, bool with_lam, bool bwd) {
@@ -148,7 +147,6 @@ inline WyWs wy_ws(const WyShape &s, int64_t n, bool with_lam, bool bwd) {
     w.gram = off;   off += align256(nm * kGramSeg * hp * hp * 8);
     w.gsum = off;   off += align256(nm * hp * hp * 8);
     w.tw = off;     off += align256(hp * hp * 8);
-    w.tm = off;     off += align256(hp * hp * 4);
     w.lam = off;    off += with_lam ? align256(np * 4) : 0;
     w.uh64 = off;   off += bwd ? align256(hp * (size_t)n * 8) : 0;
     w.total = off;
