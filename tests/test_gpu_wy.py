@@ -41,7 +41,8 @@ def make(n, h, N, dt, seed=0):
 # tails included); smaller shapes the register-resident one.
 SHAPES = [(4096, 64, 1000), (256, 10, 33), (512, 9, 100), (1024, 64, 50), (2048, 100, 40),
           (8192, 128, 20), (4096, 1, 17), (1000, 7, 31), (64, 3, 5), (8192, 64, 300),
-          (4096, 100, 129), (6144, 128, 257), (64, 100, 9), (32, 64, 40)]  # last two: h > n
+          (4096, 100, 129), (6144, 128, 257), (64, 100, 9), (32, 64, 40),  # these two: h > n
+          (6144, 50, 77)]  # resident kernel with 1024-row wave slices
 
 
 @pytest.mark.parametrize("dname", ["bf16", "f16"])
@@ -60,7 +61,7 @@ def test_wy_apply_parity(dname, n, h, N):
 
 @pytest.mark.parametrize("dname", ["bf16", "f16"])
 @pytest.mark.parametrize("n,h,N", [(512, 9, 64), (1024, 64, 40), (2048, 100, 16), (4096, 128, 133),
-                                   (8192, 64, 70)])
+                                   (8192, 64, 70), (6144, 50, 77), (4096, 64, 45)])
 def test_wy_sym_parity(dname, n, h, N):
     dt = DT[dname]
     U, X = make(n, h, N, dt, seed=3 * n + h)
@@ -136,7 +137,7 @@ def test_wy_matches_fused_fp32():
 from tests._util import rel_fro  # noqa: E402
 
 BSHAPES = [(512, 9, 100), (1024, 64, 50), (4096, 64, 300), (2048, 100, 40), (8192, 128, 64),
-           (256, 3, 1000), (64, 1, 7), (8192, 64, 131)]
+           (256, 3, 1000), (64, 1, 7), (8192, 64, 131), (6144, 50, 77)]
 
 
 @pytest.mark.parametrize("dname", ["bf16", "f16"])
