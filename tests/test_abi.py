@@ -173,3 +173,17 @@ def test_saved_record_validation():
     assert bwd(sb=nb.value - 1) == L.HH_ERR_INVALID_ARG
     assert bwd(saved=4104) == L.HH_ERR_INVALID_ARG
     assert bwd(desc=_desc()) == L.HH_ERR_UNSUPPORTED
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No fallback: without libhh.so every entry point raises instead of
+    computing anything on the host."""
+    import torch
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "libhh.so"))
+    monkeypatch.setattr(L, "_lib", None)
+    with pytest.raises(ImportError):
+        L.lib()
+    U = torch.zeros((2, 8))
+    X = torch.zeros((4, 8))
+    with pytest.raises((ImportError, ValueError)):
+        P.apply_raw(U, X)
