@@ -426,6 +426,6 @@ const char *hh_status_string(hh_status s) {
 
 const char *hh_last_error(void) { return g_last_error.c_str(); }
 
-int hh_version(void) { return 100; }
+int hh_version(void) { return 200; }  // 0.2.0: saved record, FP32 data on the WY path
 
 }  // extern "C"

@@ -187,3 +187,8 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     X = torch.zeros((4, 8))
     with pytest.raises((ImportError, ValueError)):
         P.apply_raw(U, X)
+
+
+def test_version():
+    v = P.lib().hh_version()
+    assert v >= 200 and v < 10000  # 0.x.y with the saved record and FP32 data on the WY path
