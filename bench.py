@@ -216,6 +216,11 @@ def main():
         torch.cuda.synchronize()
         ms_setup = float(np.mean([a.elapsed_time(b) for a, b in e1]))
     ms_ev = ms_call - ms_setup  # main kernel (whole step for the forward+backward workloads)
+    timed = "main kernel" if ms_setup > 0 else "whole step"
+    if ms_ev < 0.25 * ms_call:
+        # a launch-bound call (setup and launches take most of it): the difference
+        # of two short timings is noise, so the roofline uses the whole call
+        ms_ev, timed = ms_call, "whole call (launch-bound)"
 
     io_bytes = {"f32": 4, "f64": 8, "bf16": 2, "f16": 2}[comp]
     abytes, aflops = algorithmic(op, n, h, N, io_bytes, 8 if comp == "f64" else 4)
@@ -256,7 +261,7 @@ def main():
                    "op": op},
         "roofline": {"bound": bound, "achieved": ach, "peak": peak, "unit": unit,
                      "frac": ach / peak, "traffic": traffic,
-                     "kernel_ms_events": ms_ev, "call_ms_events": ms_call,
+                     "kernel_ms_events": ms_ev, "timed": timed, "call_ms_events": ms_call,
                      "setup_ms_events": ms_setup, "algorithmic_bytes": abytes,
                      "algorithmic_flops": aflops},
     }

@@ -125,7 +125,24 @@ def saved_record(op: int, desc: HHDesc, device) -> torch.Tensor:
     return torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
 
 
+# Small workspaces are kept per (device, stream) and reused: calls on one
+# stream run in order, so a later call cannot overwrite scratch space an
+# earlier call still uses.  Larger ones are allocated per call.
+_WS_CACHE_MAX = 16 << 20
+_ws_cache = {}
+
+
 def workspace(op: int, desc: HHDesc, device) -> torch.Tensor:
     nbytes = ctypes.c_size_t(0)
     check("hh_workspace_size", lib().hh_workspace_size(op, ctypes.byref(desc), ctypes.byref(nbytes)))
-    return torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=device)
+    need = max(int(nbytes.value), 256)
+    if need > _WS_CACHE_MAX:
+        return torch.empty(need, dtype=torch.uint8, device=device)
+    dev = torch.device(device)
+    key = (dev.index if dev.index is not None else torch.cuda.current_device(),
+           torch.cuda.current_stream(dev).cuda_stream)
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1 << 20), dtype=torch.uint8, device=dev)
+        _ws_cache[key] = ws
+    return ws
