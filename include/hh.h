@@ -227,6 +227,36 @@ HH_API hh_status hh_backward_saved(hh_op op, const hh_desc *d, const void *U, in
                             int64_t lddu, void *dlam, void *ws, size_t ws_bytes,
                             hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Diagonal D on either side (Sec. II-A, eq. 1: the factorisation is D times
+ * the reflector product, with D = diag(d), d in {+1, -1}^n; Result 3 puts D
+ * on the right of the product instead; Sec. III-A, eq. thesbar: D on both
+ * sides of the symmetric form).  The forward op with the input scaled by
+ * diag(d_in) and the output by diag(d_out):
+ *
+ *   HH_OP_APPLY    Y = diag(d_out) Q diag(d_in) X
+ *   HH_OP_APPLY_T  Y = diag(d_out) Q^T diag(d_in) X
+ *   HH_OP_SYM      Y = diag(d_out) Q diag(lam) Q^T diag(d_in) X
+ *   HH_OP_MAHAL    dist_j = sum_i lam_i (Q^T diag(d_in) (xa_j - xb_j))_i^2
+ *
+ * so eq. 1's operator U = D Q is HH_OP_APPLY with d_out = d and its transpose
+ * HH_OP_APPLY_T with d_in = d; Result 3's Q D is HH_OP_APPLY with d_in = d
+ * (transpose: HH_OP_APPLY_T with d_out = d); eq. thesbar is HH_OP_SYM with
+ * d_in = d_out = d, and its metric HH_OP_MAHAL with d_in = d.  d_in and d_out
+ * are device arrays of n param_dtype values, each nullable (null = identity),
+ * aligned to their element size; d_out must be null for HH_OP_MAHAL.  Entries
+ * of +-1 keep the operator orthonormal; other values are applied as given.
+ * Arguments otherwise as for hh_apply / hh_apply_T / hh_sym_apply (Xb, ldb
+ * ignored) and hh_mahalanobis (X, ldx = Xa, lda; Y = dist, ldy ignored), same
+ * workspace.  The diagonals are multiplied in registers on the vectors' one
+ * pass through the chip (no extra pass over HBM).  FUSED algorithm only
+ * (HH_ERR_UNSUPPORTED on WY), at the fused forward's sizes. */
+HH_API hh_status hh_forward_signed(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
+                            const void *lam, const void *d_in, const void *d_out,
+                            const void *X, int64_t ldx, const void *Xb, int64_t ldb,
+                            void *Y, int64_t ldy, void *ws, size_t ws_bytes,
+                            hipStream_t stream);
+
 /* Static text for a status code. */
 HH_API const char *hh_status_string(hh_status s);
 

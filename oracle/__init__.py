@@ -137,6 +137,32 @@ def mahal(U, lam, Xa, Xb):
     return d
 
 
+def signed(op, U, X, d_in=None, d_out=None, lam=None, Xb=None):
+    """A forward op with diagonal matrices on either side, written out as
+    products: diag(d_out) op(diag(d_in) X) for op "apply" (Q), "apply_T" (Q^T)
+    and "sym" (Q diag(lam) Q^T); for "mahal" the distances of diag(d_in)(xa - xb).
+    Eq. 1 puts D = diag(d) on the left of the reflector product (d_out = d with
+    "apply"), Result 3 on its right (d_in = d), eq. thesbar on both sides of the
+    symmetric form (d_in = d_out = d).  Rows of X are vectors, so diag(d) X is
+    the columnwise product X * d."""
+    X = _f64(X)
+    n = X.shape[1]
+    din = np.ones(n) if d_in is None else _f64(d_in)
+    dout = np.ones(n) if d_out is None else _f64(d_out)
+    if op == "mahal":
+        assert d_out is None
+        return mahal(U, lam, X * din, _f64(Xb) * din)
+    if op == "apply":
+        Y = apply(U, X * din)
+    elif op == "apply_T":
+        Y = apply(U, X * din, trans=True)
+    elif op == "sym":
+        Y = sym(U, lam, X * din)
+    else:
+        raise ValueError(op)
+    return Y * dout
+
+
 def apply_bwd(U, X, dY, trans: bool = False):
     """Gradients of L = <dY, op(X)> for op = Q (trans=False) or Q^T.
 

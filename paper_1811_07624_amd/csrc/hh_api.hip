@@ -133,11 +133,15 @@ static FusedWs fused_ws(hh_op op, const FusedPlan &p) {
     return w;
 }
 
-static hh_status make_fused_plan(const hh_desc *d, FusedPlan *p) {
+static hh_status make_fused_plan(const hh_desc *d, FusedPlan *p, int ndiag = 0) {
     if (!fused_plan(d->compute_dtype, d->n, d->h, d->N, p))
         return fail(HH_ERR_UNSUPPORTED,
                     "fused path supports n <= %d for this dtype (n = %lld)",
                     d->compute_dtype == HH_F64 ? 4096 : 8192, (long long)d->n);
+    if (ndiag > 0 && !fused_plan(d->compute_dtype, d->n, d->h, d->N, p, ndiag))
+        return fail(HH_ERR_UNSUPPORTED,
+                    "%d diagonal(s) and the spectrum do not fit in on-chip memory beside a reflector "
+                    "(n = %lld)", ndiag, (long long)d->n);
     return HH_OK;
 }
 
@@ -156,7 +160,8 @@ static int aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 static hh_status forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
                          const void *lam, const void *X, int64_t ldx, const void *Xb,
                          int64_t ldb, void *Y, int64_t ldy, void *ws, size_t ws_bytes,
-                         hipStream_t st, void *saved = nullptr, size_t saved_bytes = 0) {
+                         hipStream_t st, void *saved = nullptr, size_t saved_bytes = 0,
+                         const void *din = nullptr, const void *dout = nullptr) {
     Algo algo;
     HH_TRY(check_desc(d, &algo));
     const int64_t n = d->n, h = d->h, N = d->N;
@@ -164,13 +169,17 @@ static hh_status forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
     HH_TRY(check_ld(op == HH_OP_MAHAL ? "lda" : "ldx", ldx, n));
     if (op == HH_OP_MAHAL) HH_TRY(check_ld("ldb", ldb, n));
     else HH_TRY(check_ld("ldy", ldy, n));
-    if (algo == Algo::WY)
+    if (op == HH_OP_MAHAL && dout)
+        return fail(HH_ERR_INVALID_ARG, "a distance has no output diagonal (d_out must be null)");
+    if (algo == Algo::WY) {
+        if (din || dout) return fail(HH_ERR_UNSUPPORTED, "diagonals are applied on the fused path only");
         return wy_forward(op, d, U, ldu, lam, X, ldx, Xb, ldb, Y, ldy, saved, saved_bytes, ws,
                           ws_bytes, st);
+    }
     if (saved) return fail(HH_ERR_UNSUPPORTED, "a coefficient record exists on the WY path only");
 
     FusedPlan p;
-    HH_TRY(make_fused_plan(d, &p));
+    HH_TRY(make_fused_plan(d, &p, (din ? 1 : 0) + (dout ? 1 : 0)));
     const FusedWs w = fused_ws(op, p);
     if (N == 0) return HH_OK;
     if (h > 0) HH_TRY(check_ptr("U", U));
@@ -202,6 +211,8 @@ static hh_status forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
     a.ut = base + w.ut;
     a.tau = base + w.tau;
     a.lam = base + w.lam;
+    a.din = din;
+    a.dout = dout;
     a.n = (int)n;
     a.h = (int)h;
     a.npad = p.s.npad;
@@ -399,6 +410,22 @@ hh_status hh_forward_save(hh_op op, const hh_desc *d, const void *U, int64_t ldu
                    ws_bytes, stream, saved, saved_bytes);
 }
 
+hh_status hh_forward_signed(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
+                            const void *lam, const void *d_in, const void *d_out, const void *X,
+                            int64_t ldx, const void *Xb, int64_t ldb, void *Y, int64_t ldy,
+                            void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (op != HH_OP_APPLY && op != HH_OP_APPLY_T && op != HH_OP_SYM && op != HH_OP_MAHAL)
+        return fail(HH_ERR_INVALID_ARG, "op must be a forward op");
+    if (!d) return fail(HH_ERR_INVALID_ARG, "desc must not be null");
+    const size_t es = dtype_size(d->param_dtype);
+    if (es == 0) return fail(HH_ERR_INVALID_ARG, "unknown param_dtype");
+    if (((uintptr_t)d_in % es) != 0 || ((uintptr_t)d_out % es) != 0)
+        return fail(HH_ERR_INVALID_ARG, "d_in and d_out must be aligned to their element size");
+    return forward(op, d, U, ldu, (op == HH_OP_SYM || op == HH_OP_MAHAL) ? lam : nullptr, X, ldx,
+                   op == HH_OP_MAHAL ? Xb : nullptr, ldb, Y, ldy, ws, ws_bytes, stream, nullptr, 0,
+                   d_in, d_out);
+}
+
 hh_status hh_backward_saved(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
                             const void *lam, const void *X, int64_t ldx, const void *saved,
                             size_t saved_bytes, const void *dY, int64_t lddy, void *dX,
@@ -426,6 +453,6 @@ const char *hh_status_string(hh_status s) {
 
 const char *hh_last_error(void) { return g_last_error.c_str(); }
 
-int hh_version(void) { return 200; }  // 0.2.0: saved record, FP32 data on the WY path
+int hh_version(void) { return 300; }  // 0.3.0: diagonals on either side (hh_forward_signed)
 
 }  // extern "C"

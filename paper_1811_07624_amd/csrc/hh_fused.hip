@@ -38,7 +38,9 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
     const int n = a.n, h = a.h, npad = a.npad, hc = a.hc;
     T *sU = reinterpret_cast<T *>(smem);
     T *sLam = sU + (size_t)hc * npad;
-    T *sTau = sLam + npad;  // tau of the reflectors of the current chunk
+    T *sDin = sLam + npad;                         // diagonal on the input (if given)
+    T *sDout = sDin + (a.din ? npad : 0);          // diagonal on the output (if given)
+    T *sTau = sDout + (a.dout ? npad : 0);         // tau of the reflectors of the current chunk
     const T *gU = static_cast<const T *>(a.ut);
     const T *gTau = static_cast<const T *>(a.tau);
 
@@ -52,6 +54,13 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
         const VT *src = static_cast<const VT *>(a.lam);
         for (int i = tid; i < npad / W; i += kThreads) reinterpret_cast<VT *>(sLam)[i] = src[i];
     }
+    // the caller's diagonals hold n entries (no padding, no alignment assumed)
+    auto stage_diag = [&](T *dst, const void *src) {
+        const T *d = static_cast<const T *>(src);
+        for (int i = tid; i < npad; i += kThreads) dst[i] = i < n ? d[i] : (T)0;
+    };
+    if (a.din) stage_diag(sDin, a.din);
+    if (a.dout) stage_diag(sDout, a.dout);
     __syncthreads();
 
     const int nchunks = h > 0 ? (h + hc - 1) / hc : 0;
@@ -96,6 +105,17 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
             for (int i = 0; i < NC; ++i)
 #pragma unroll
                 for (int q = 0; q < W; ++q) x[v][i * W + q] = fmat(coef, uv[i][q], x[v][i * W + q]);
+        }
+    };
+    // x <- diag(d) x on the lane's slices (d staged in LDS like the spectrum)
+    auto scale = [&](T(&x)[VPL][E], const T *sd) {
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            VT l = *reinterpret_cast<const VT *>(sd + i * STR + c * W);
+#pragma unroll
+            for (int v = 0; v < VPL; ++v)
+#pragma unroll
+                for (int q = 0; q < W; ++q) x[v][i * W + q] *= l[q];
         }
     };
     auto run_up = [&](T(&x)[VPL][E]) {  // k = 0 .. h-1  (Q^T: H_1 first)
@@ -197,6 +217,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
                 }
             }
         }
+        if (a.din) scale(x, sDin);
         if constexpr (OP == F_APPLY) run_down(x);
         if constexpr (OP == F_APPLY_T || OP == F_SYM || OP == F_MAHAL) run_up(x);
         if constexpr (OP == F_SYM) {
@@ -210,6 +231,8 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
             }
             run_down(x);
         }
+        if constexpr (OP != F_MAHAL)
+            if (a.dout) scale(x, sDout);
 #pragma unroll
         for (int v = 0; v < VPL; ++v) {
             const int64_t j = j0 + v;
@@ -318,7 +341,7 @@ bool fused_shape(hh_dtype t, int64_t n, FusedShape *s) {
     return true;
 }
 
-bool fused_plan(hh_dtype t, int64_t n, int64_t h, int64_t N, FusedPlan *p) {
+bool fused_plan(hh_dtype t, int64_t n, int64_t h, int64_t N, FusedPlan *p, int ndiag) {
     p->t = t;
     p->n = n;
     p->h = h;
@@ -326,8 +349,10 @@ bool fused_plan(hh_dtype t, int64_t n, int64_t h, int64_t N, FusedPlan *p) {
     if (!fused_shape(t, n, &p->s)) return false;
     const size_t es = (t == HH_F64) ? 8 : 4;
     const size_t vec_bytes = (size_t)p->s.npad * es;
-    const size_t fixed = vec_bytes;  // spectrum
-    const size_t budget = (p->s.lpv == 64 && p->s.wpb == 8) ? kLdsBudgetWide : kLdsBudget;
+    const size_t fixed = vec_bytes * (1 + (size_t)ndiag);  // spectrum and the diagonals
+    size_t budget = (p->s.lpv == 64 && p->s.wpb == 8) ? kLdsBudgetWide : kLdsBudget;
+    // with diagonals, a large n runs with fewer blocks per compute unit
+    if (ndiag > 0 && fixed + vec_bytes > budget) budget = kLdsBudgetWide;
     if (fixed + vec_bytes > budget) return false;
     const int64_t fit = (int64_t)((budget - fixed) / vec_bytes);
     p->hc = (int)std::max<int64_t>(1, std::min<int64_t>(h, fit));

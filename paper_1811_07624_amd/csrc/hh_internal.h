@@ -167,6 +167,8 @@ struct FusedFwdArgs {
     const void *ut;
     const void *tau;
     const void *lam;
+    const void *din;   // n diagonal entries applied to the input, or null
+    const void *dout;  // n diagonal entries applied to the output, or null
     int n, h, npad, hc;
     int64_t N;
     int vec_ok;  // 16-byte accesses are legal for every data operand
@@ -174,6 +176,8 @@ struct FusedFwdArgs {
 
 hipError_t launch_fused_fwd(const FusedPlan &p, FusedOp op, const FusedFwdArgs &a,
                             hipStream_t st);
-bool fused_plan(hh_dtype t, int64_t n, int64_t h, int64_t N, FusedPlan *p);
+// ndiag: how many n-vectors of diagonal entries the kernel stages beside the
+// spectrum (0, 1 or 2)
+bool fused_plan(hh_dtype t, int64_t n, int64_t h, int64_t N, FusedPlan *p, int ndiag = 0);
 
 }  // namespace hh

@@ -136,6 +136,44 @@ def mahal_raw(U, lam, Xa, Xb, compute=None, algo="auto"):
     return d
 
 
+def signed_raw(op, U, X, d_in=None, d_out=None, lam=None, Xb=None, compute=None, algo="auto",
+               out=None):
+    """The forward op ("apply", "apply_T", "sym" or "mahal") with diagonals on
+    either side: diag(d_out) op(diag(d_in) X), or for "mahal" the distances of
+    diag(d_in) (xa - xb).  Eq. 1's D Q is op "apply" with d_out = d, eq.
+    thesbar's D Q diag(lam) Q^T D is "sym" with d_in = d_out = d.  Fused
+    (FP32/FP64) algorithm only."""
+    ops = {"apply": L.HH_OP_APPLY, "apply_T": L.HH_OP_APPLY_T, "sym": L.HH_OP_SYM,
+           "mahal": L.HH_OP_MAHAL}
+    hop = ops[op]
+    _check_dev(U, X, *[t for t in (d_in, d_out, lam, Xb) if t is not None])
+    X = _rows(X)
+    param, io, comp = _cfg(X, compute)
+    U = _param(U, param)
+    N, n = X.shape
+    h = U.shape[0]
+    desc = L.make_desc(n, h, N, param, io, comp, algo)
+    for name, t in (("d_in", d_in), ("d_out", d_out), ("lam", lam)):
+        if t is not None and t.numel() != n:
+            raise ValueError(f"{name} must hold n = {n} values, got {t.numel()}")
+    d_in = None if d_in is None else _param(d_in, param)
+    d_out = None if d_out is None else _param(d_out, param)
+    lam = None if lam is None else _param(lam, param)
+    if hop == L.HH_OP_MAHAL:
+        Xb = _rows(Xb)
+        Y = torch.empty((N,), dtype=param, device=X.device) if out is None else out
+        ldy, ldb = 1, L.ld(Xb)
+    else:
+        Y = torch.empty((N, n), dtype=io, device=X.device) if out is None else out
+        ldy, ldb = L.ld(Y), 0
+    ws = L.workspace(hop, desc, X.device)
+    L.check("hh_forward_signed", L.lib().hh_forward_signed(
+        hop, ctypes.byref(desc), L.ptr(U), max(n, U.stride(0) if h else n), L.ptr(lam),
+        L.ptr(d_in), L.ptr(d_out), L.ptr(X), L.ld(X), L.ptr(Xb), ldb, L.ptr(Y), ldy,
+        L.ptr(ws), ws.numel(), L.stream_of(X)))
+    return Y
+
+
 def apply_bwd_raw(U, X, dY, trans=False, compute=None, algo="auto", need_dX=True, need_dU=True,
                   saved=None):
     """Gradients of Y = Q X (or Q^T X); saved: the forward's record (WY only)."""

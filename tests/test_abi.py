@@ -175,6 +175,26 @@ def test_saved_record_validation():
     assert bwd(desc=_desc()) == L.HH_ERR_UNSUPPORTED
 
 
+def test_signed_validation():
+    # fake, aligned pointers: every failure below is caught before any launch
+    v = ctypes.c_void_p
+    lib = P.lib()
+
+    def fwd(op=L.HH_OP_APPLY, desc=None, d_in=0, d_out=0, lam=None, ld=8):
+        dp = ctypes.byref(desc if desc is not None else _desc()) if desc is not False else None
+        return lib.hh_forward_signed(op, dp, v(1024), ld, v(lam) if lam else None,
+                                     v(d_in) if d_in else None, v(d_out) if d_out else None,
+                                     v(2048), ld, v(4096), ld, v(3072), ld, v(8192), 1 << 20, None)
+    assert fwd(op=L.HH_OP_APPLY_BWD, d_in=5120) == L.HH_ERR_INVALID_ARG
+    assert fwd(desc=False, d_in=5120) == L.HH_ERR_INVALID_ARG
+    assert fwd(d_in=5122) == L.HH_ERR_INVALID_ARG                     # not aligned to 4 bytes
+    assert fwd(d_out=5122) == L.HH_ERR_INVALID_ARG
+    assert fwd(desc=_desc(p=L.HH_F64, io=L.HH_F64, c=L.HH_F64), d_in=5124) == L.HH_ERR_INVALID_ARG
+    assert fwd(op=L.HH_OP_MAHAL, d_out=5120, lam=6144) == L.HH_ERR_INVALID_ARG  # a distance has no output side
+    assert fwd(desc=_wy_desc(), d_in=5120, ld=256) == L.HH_ERR_UNSUPPORTED      # fused path only
+    assert fwd(desc=_wy_desc(), d_out=5120, ld=256) == L.HH_ERR_UNSUPPORTED
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     """No fallback: without libhh.so every entry point raises instead of
     computing anything on the host."""
@@ -191,4 +211,4 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
 
 def test_version():
     v = P.lib().hh_version()
-    assert v >= 200 and v < 10000  # 0.x.y with the saved record and FP32 data on the WY path
+    assert v >= 300 and v < 10000  # 0.x.y with the saved record, FP32 data on the WY path and diagonals

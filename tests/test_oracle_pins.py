@@ -382,3 +382,64 @@ def test_bwd_invariants():
     U[2] = 0.0
     _, dU = oracle.apply_bwd(U, X, G)
     assert np.all(dU[2] == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Diagonal D on either side (eq. 1, Result 3, eq. thesbar)
+
+@pytest.mark.parametrize("n,h", [(12, 5), (40, 17)])
+def test_signed_result3_identity_block(n, h):
+    """Eq. ReflectorStructure with D in place: D J_h ... J_1 U = [I_h 0; 0 D_1 U~]
+    with D_1 U~ of positive diagonal, once D = diag(sign of the top block,
+    sign(diag U~)) is put on the output of Q^T = J_h ... J_1 (the transpose of
+    Result 3's J_1 ... J_h D); and Result 3's error ||U - J_1 ... J_h D||_F^2 =
+    2(n - h) - 2 tr(D_1 U~), with J_1 ... J_h D applied to the identity as Q
+    with D on its input."""
+    U0 = random_orthonormal(n, 300 + n + h)
+    V, _ = oracle.householder_qr(U0)
+    Vh = V[:h]
+    plain = oracle.apply(Vh, U0.T, trans=True).T
+    d = np.concatenate([np.sign(np.diag(plain)[:h]), np.sign(np.diag(plain[h:, h:]))])
+    B = oracle.signed("apply_T", Vh, U0.T, d_out=d).T
+    assert np.abs(B[:h, :h] - np.eye(h)).max() < 1e-13
+    assert np.abs(B[:h, h:]).max() < 1e-13 and np.abs(B[h:, :h]).max() < 1e-13
+    assert np.all(np.diag(B[h:, h:]) > 0)
+    QD = oracle.signed("apply", Vh, np.eye(n), d_in=d).T   # column j: Q D e_j
+    err = np.linalg.norm(U0 - QD) ** 2
+    assert abs(err - (2 * (n - h) - 2 * np.trace(B[h:, h:]))) < 1e-11
+    # D on the other side of Q^T does not give the identity block
+    Bw = oracle.signed("apply_T", Vh, U0.T, d_in=d).T
+    assert np.abs(Bw[:h, :h] - np.eye(h)).max() > 1e-3 or np.abs(Bw[h:, :h]).max() > 1e-3
+
+
+def test_signed_sym_is_symmetric_with_spectrum_lam():
+    """Eq. thesbar: D Q diag(lam) Q^T D is symmetric with eigenvalues lam (an
+    orthonormal similarity of diag(lam)); with D on one side only it is not
+    symmetric.  Its metric gives (x - y)^T S (x - y)."""
+    n, h = 24, 6
+    rng = _rng(5)
+    U = rng.standard_normal((h, n))
+    lam = rng.uniform(0.1, 3.0, n)
+    d = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    S = oracle.signed("sym", U, np.eye(n), d_in=d, d_out=d, lam=lam)   # row j: S e_j
+    assert np.abs(S - S.T).max() < 1e-13
+    assert np.abs(np.linalg.eigvalsh(S) - np.sort(lam)).max() < 1e-12
+    S1 = oracle.signed("sym", U, np.eye(n), d_out=d, lam=lam)
+    assert np.abs(S1 - S1.T).max() > 1e-3
+    Xa, Xb = rng.standard_normal((7, n)), rng.standard_normal((7, n))
+    dist = oracle.signed("mahal", U, Xa, d_in=d, lam=lam, Xb=Xb)
+    ref = np.einsum("ji,ik,jk->j", Xa - Xb, S, Xa - Xb)
+    assert np.abs(dist - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_signed_identity_diagonal_reduces_to_plain_ops():
+    """d = 1 everywhere is D = I: the plain ops, bit for bit."""
+    n, h, N = 30, 4, 5
+    rng = _rng(6)
+    U, X, Xb = rng.standard_normal((h, n)), rng.standard_normal((N, n)), rng.standard_normal((N, n))
+    lam = rng.uniform(0.1, 2.0, n)
+    one = np.ones(n)
+    assert np.array_equal(oracle.signed("apply", U, X, d_in=one, d_out=one), oracle.apply(U, X))
+    assert np.array_equal(oracle.signed("apply_T", U, X, d_in=one, d_out=one), oracle.apply(U, X, trans=True))
+    assert np.array_equal(oracle.signed("sym", U, X, d_in=one, d_out=one, lam=lam), oracle.sym(U, lam, X))
+    assert np.array_equal(oracle.signed("mahal", U, X, d_in=one, lam=lam, Xb=Xb), oracle.mahal(U, lam, X, Xb))
