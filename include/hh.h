@@ -257,6 +257,22 @@ HH_API hh_status hh_forward_signed(hh_op op, const hh_desc *d, const void *U, in
                             void *Y, int64_t ldy, void *ws, size_t ws_bytes,
                             hipStream_t stream);
 
+/* Gradients of L = <dY, Y> for the Y of hh_forward_signed (same op, d_in,
+ * d_out): with X' = diag(d_in) X and dY' = diag(d_out) dY, dU and dlam are
+ * those of the plain op at (X', dY') and dX = diag(d_in) times the plain op's
+ * dX at (X', dY'); for HH_OP_MAHAL_BWD (dY = ddist, N values; d_out null)
+ * dXa = -dXb = diag(d_in) times the plain dXa at diag(d_in)(xa - xb).
+ * Arguments otherwise as for the backward entry points above (Xb, dXb:
+ * HH_OP_MAHAL_BWD only; lam, dlam: HH_OP_SYM_BWD and HH_OP_MAHAL_BWD only;
+ * lddy ignored for HH_OP_MAHAL_BWD), same workspace and sizes.  FUSED
+ * algorithm only (HH_ERR_UNSUPPORTED on WY). */
+HH_API hh_status hh_backward_signed(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
+                             const void *lam, const void *d_in, const void *d_out,
+                             const void *X, int64_t ldx, const void *Xb, int64_t ldb,
+                             const void *dY, int64_t lddy, void *dX, void *dXb,
+                             int64_t lddx, void *dU, int64_t lddu, void *dlam, void *ws,
+                             size_t ws_bytes, hipStream_t stream);
+
 /* Static text for a status code. */
 HH_API const char *hh_status_string(hh_status s);
 

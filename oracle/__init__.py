@@ -163,6 +163,30 @@ def signed(op, U, X, d_in=None, d_out=None, lam=None, Xb=None):
     return Y * dout
 
 
+def signed_bwd(op, U, X, dY, d_in=None, d_out=None, lam=None, Xb=None):
+    """Gradients of L = <dY, signed(op, U, X, d_in, d_out, lam, Xb)> by the
+    chain rule through the two diagonal products: the plain op's gradients at
+    X' = diag(d_in) X with upstream diag(d_out) dY, and dX = diag(d_in) dX'.
+    Returns (dX, dU, dlam) (dlam None unless "sym"), or for "mahal" (dY = the
+    N distance weights) (dXa, dXb, dU, dlam)."""
+    X = _f64(X)
+    n = X.shape[1]
+    din = np.ones(n) if d_in is None else _f64(d_in)
+    dout = np.ones(n) if d_out is None else _f64(d_out)
+    if op == "mahal":
+        assert d_out is None
+        dXa, dXb, dU, dlam = mahal_bwd(U, lam, X * din, _f64(Xb) * din, dY)
+        return dXa * din, dXb * din, dU, dlam
+    G = _f64(dY) * dout
+    if op in ("apply", "apply_T"):
+        dXp, dU = apply_bwd(U, X * din, G, trans=(op == "apply_T"))
+        return dXp * din, dU, None
+    if op == "sym":
+        dXp, dU, dlam = sym_bwd(U, lam, X * din, G)
+        return dXp * din, dU, dlam
+    raise ValueError(op)
+
+
 def apply_bwd(U, X, dY, trans: bool = False):
     """Gradients of L = <dY, op(X)> for op = Q (trans=False) or Q^T.
 

@@ -236,7 +236,8 @@ static hh_status backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu
                           int64_t ldb, const void *G, int64_t ldg, void *dX, void *dXb,
                           int64_t lddx, void *dU, int64_t lddu, void *dlam, void *ws,
                           size_t ws_bytes, hipStream_t st, const void *saved = nullptr,
-                          size_t saved_bytes = 0) {
+                          size_t saved_bytes = 0, const void *din = nullptr,
+                          const void *dout = nullptr) {
     Algo algo;
     HH_TRY(check_desc(d, &algo));
     const int64_t n = d->n, h = d->h, N = d->N;
@@ -246,6 +247,10 @@ static hh_status backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu
     else HH_TRY(check_ld("lddy", ldg, n));
     if (dX || dXb) HH_TRY(check_ld("lddx", lddx, n));
     if (dU && h > 0) HH_TRY(check_ld("lddu", lddu, n));
+    if (op == HH_OP_MAHAL_BWD && dout)
+        return fail(HH_ERR_INVALID_ARG, "a distance has no output diagonal (d_out must be null)");
+    if (algo == Algo::WY && (din || dout))
+        return fail(HH_ERR_UNSUPPORTED, "diagonals are applied on the fused path only");
     if (algo == Algo::WY)
         return wy_backward(op, d, U, ldu, lam, X, ldx, Xb, ldb, G, ldg, dX, dXb, lddx, dU, lddu,
                            dlam, saved, saved_bytes, ws, ws_bytes, st);
@@ -297,6 +302,8 @@ static hh_status backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu
     a.lddu = lddu;
     a.dlam = dlam;
     a.scratch = base + w.bwd;
+    a.din = din;
+    a.dout = dout;
     a.n = (int)n;
     a.h = (int)h;
     a.npad = p.s.npad;
@@ -426,6 +433,26 @@ hh_status hh_forward_signed(hh_op op, const hh_desc *d, const void *U, int64_t l
                    d_in, d_out);
 }
 
+hh_status hh_backward_signed(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
+                             const void *lam, const void *d_in, const void *d_out, const void *X,
+                             int64_t ldx, const void *Xb, int64_t ldb, const void *dY, int64_t lddy,
+                             void *dX, void *dXb, int64_t lddx, void *dU, int64_t lddu, void *dlam,
+                             void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (op != HH_OP_APPLY_BWD && op != HH_OP_APPLY_T_BWD && op != HH_OP_SYM_BWD &&
+        op != HH_OP_MAHAL_BWD)
+        return fail(HH_ERR_INVALID_ARG, "op must be a backward op");
+    if (!d) return fail(HH_ERR_INVALID_ARG, "desc must not be null");
+    const size_t es = dtype_size(d->param_dtype);
+    if (es == 0) return fail(HH_ERR_INVALID_ARG, "unknown param_dtype");
+    if (((uintptr_t)d_in % es) != 0 || ((uintptr_t)d_out % es) != 0)
+        return fail(HH_ERR_INVALID_ARG, "d_in and d_out must be aligned to their element size");
+    const bool mahal = op == HH_OP_MAHAL_BWD;
+    const bool has_lam = op == HH_OP_SYM_BWD || mahal;
+    return backward(op, d, U, ldu, has_lam ? lam : nullptr, X, ldx, mahal ? Xb : nullptr, ldb, dY,
+                    mahal ? 0 : lddy, dX, mahal ? dXb : nullptr, lddx, dU, lddu,
+                    has_lam ? dlam : nullptr, ws, ws_bytes, stream, nullptr, 0, d_in, d_out);
+}
+
 hh_status hh_backward_saved(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
                             const void *lam, const void *X, int64_t ldx, const void *saved,
                             size_t saved_bytes, const void *dY, int64_t lddy, void *dX,
@@ -453,6 +480,6 @@ const char *hh_status_string(hh_status s) {
 
 const char *hh_last_error(void) { return g_last_error.c_str(); }
 
-int hh_version(void) { return 300; }  // 0.3.0: diagonals on either side (hh_forward_signed)
+int hh_version(void) { return 300; }  // 0.3.0: diagonals on either side (hh_forward_signed, hh_backward_signed)
 
 }  // extern "C"

@@ -21,6 +21,8 @@ struct FusedBwdArgs {
     int64_t lddu;
     void *dlam;       // nullable
     void *scratch;    // per-block partial sums
+    const void *din;  // n diagonal entries on the forward's input, or null
+    const void *dout; // n diagonal entries on the forward's output, or null
     int n, h, npad;
     int64_t N;
     int vec_ok;

@@ -271,6 +271,18 @@ __global__ __launch_bounds__(kThreads) void k_fused_bwd(FusedBwdArgs a, int k0, 
         }
     };
     auto lam_chunk = [&](int i) { return *reinterpret_cast<const VT *>(sLam + i * STR + lane * W); };
+    // x <- diag(d) x for the caller's n diagonal entries (read through the
+    // caches; entries past n are zero in x already)
+    auto scale = [&](T(&x)[E], const void *dv) {
+        const T *d = static_cast<const T *>(dv);
+#pragma unroll
+        for (int i = 0; i < NC; ++i)
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const int e = i * STR + lane * W + q;
+                x[i * W + q] *= (e < n) ? d[e] : (T)0;
+            }
+    };
 
     const int64_t vpb = (int64_t)kWPB * V;
     for (int64_t b0 = (int64_t)blockIdx.x * vpb; b0 < a.N; b0 += (int64_t)gridDim.x * vpb) {
@@ -286,11 +298,17 @@ __global__ __launch_bounds__(kThreads) void k_fused_bwd(FusedBwdArgs a, int k0, 
                 for (int e = 0; e < E; ++e) s[v][e] -= g[v][e];
             }
         }
+        if (a.din)
+#pragma unroll
+            for (int v = 0; v < V; ++v) scale(s[v], a.din);
         if constexpr (OP == B_APPLY || OP == B_APPLY_T) {
             constexpr bool up = (OP == B_APPLY_T);
             fwd_chain(up, s, 0);
 #pragma unroll
             for (int v = 0; v < V; ++v) load_vec(g[v], static_cast<const T *>(a.G), a.ldg, j0 + v, j0 + v < a.N);
+            if (a.dout)
+#pragma unroll
+                for (int v = 0; v < V; ++v) scale(g[v], a.dout);
             rev_chain(up, s, g, 0);
         } else if constexpr (OP == B_SYM) {
             fwd_chain(true, s, 0);
@@ -309,6 +327,9 @@ __global__ __launch_bounds__(kThreads) void k_fused_bwd(FusedBwdArgs a, int k0, 
             fwd_chain(false, s, h);
 #pragma unroll
             for (int v = 0; v < V; ++v) load_vec(g[v], static_cast<const T *>(a.G), a.ldg, j0 + v, j0 + v < a.N);
+            if (a.dout)
+#pragma unroll
+                for (int v = 0; v < V; ++v) scale(g[v], a.dout);
             rev_chain(false, s, g, h);  // g = Q^T dY
 #pragma unroll
             for (int i = 0; i < NC; ++i) {
@@ -344,6 +365,7 @@ __global__ __launch_bounds__(kThreads) void k_fused_bwd(FusedBwdArgs a, int k0, 
         if (write_dx) {
 #pragma unroll
             for (int v = 0; v < V; ++v) {
+                if (a.din) scale(g[v], a.din);
                 const int64_t j = j0 + v;
                 if (j < a.N) {
                     if (a.dX) store_vec(g[v], (T)1, static_cast<T *>(a.dX), a.lddx, j);

@@ -254,6 +254,48 @@ def mahal_bwd_raw(U, lam, Xa, Xb, dd, compute=None, algo="auto", need_dX=True, n
     return dXa, dXb, dU, dlam
 
 
+def signed_bwd_raw(op, U, X, dY, d_in=None, d_out=None, lam=None, Xb=None, compute=None,
+                   algo="auto"):
+    """Gradients of <dY, signed_raw(op, U, X, d_in, d_out, lam, Xb)>: returns
+    (dX, dU, dlam) for "apply", "apply_T" and "sym" (dlam None unless "sym"),
+    (dXa, dXb, dU, dlam) for "mahal" (dY = the N distance weights)."""
+    ops = {"apply": L.HH_OP_APPLY_BWD, "apply_T": L.HH_OP_APPLY_T_BWD, "sym": L.HH_OP_SYM_BWD,
+           "mahal": L.HH_OP_MAHAL_BWD}
+    hop = ops[op]
+    _check_dev(U, X, dY, *[t for t in (d_in, d_out, lam, Xb) if t is not None])
+    X = _rows(X)
+    param, io, comp = _cfg(X, compute)
+    U = _param(U, param)
+    N, n = X.shape
+    h = U.shape[0]
+    for name, t in (("d_in", d_in), ("d_out", d_out), ("lam", lam)):
+        if t is not None and t.numel() != n:
+            raise ValueError(f"{name} must hold n = {n} values, got {t.numel()}")
+    d_in = None if d_in is None else _param(d_in, param)
+    d_out = None if d_out is None else _param(d_out, param)
+    lam = None if lam is None else _param(lam, param)
+    mahal = hop == L.HH_OP_MAHAL_BWD
+    if mahal:
+        Xb = _rows(Xb)
+        dY = _param(dY, param)
+        lddy, ldb = 0, L.ld(Xb)
+    else:
+        dY = _rows(dY)
+        lddy, ldb = L.ld(dY), 0
+    desc = L.make_desc(n, h, N, param, io, comp, algo)
+    dX = torch.empty((N, n), dtype=io, device=X.device)
+    dXb = torch.empty((N, n), dtype=io, device=X.device) if mahal else None
+    dU = torch.empty((h, n), dtype=param, device=X.device)
+    dlam = torch.empty((n,), dtype=param, device=X.device) if hop in (L.HH_OP_SYM_BWD, L.HH_OP_MAHAL_BWD) else None
+    ws = L.workspace(hop, desc, X.device)
+    L.check("hh_backward_signed", L.lib().hh_backward_signed(
+        hop, ctypes.byref(desc), L.ptr(U), max(n, U.stride(0) if h else n), L.ptr(lam),
+        L.ptr(d_in), L.ptr(d_out), L.ptr(X), L.ld(X), L.ptr(Xb), ldb, L.ptr(dY), lddy,
+        L.ptr(dX), L.ptr(dXb), n, L.ptr(dU), n, L.ptr(dlam), L.ptr(ws), ws.numel(),
+        L.stream_of(X)))
+    return (dX, dXb, dU, dlam) if mahal else (dX, dU, dlam)
+
+
 # --------------------------------------------------------------------------
 # autograd
 # --------------------------------------------------------------------------

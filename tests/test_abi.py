@@ -195,6 +195,22 @@ def test_signed_validation():
     assert fwd(desc=_wy_desc(), d_out=5120, ld=256) == L.HH_ERR_UNSUPPORTED
 
 
+def test_signed_backward_validation():
+    v = ctypes.c_void_p
+    lib = P.lib()
+
+    def bwd(op=L.HH_OP_APPLY_BWD, desc=None, d_in=0, d_out=0, ld=8):
+        dp = ctypes.byref(desc if desc is not None else _desc())
+        return lib.hh_backward_signed(op, dp, v(1024), ld, v(6144), v(d_in) if d_in else None,
+                                      v(d_out) if d_out else None, v(2048), ld, v(4096), ld,
+                                      v(3072), ld, v(5120), v(7168), ld, v(9216), ld, v(10240),
+                                      v(8192), 1 << 20, None)
+    assert bwd(op=L.HH_OP_APPLY, d_in=12288) == L.HH_ERR_INVALID_ARG
+    assert bwd(d_in=12290) == L.HH_ERR_INVALID_ARG                    # not aligned to 4 bytes
+    assert bwd(op=L.HH_OP_MAHAL_BWD, d_out=12288) == L.HH_ERR_INVALID_ARG
+    assert bwd(desc=_wy_desc(), d_in=12288, ld=256) == L.HH_ERR_UNSUPPORTED
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     """No fallback: without libhh.so every entry point raises instead of
     computing anything on the host."""

@@ -14,7 +14,7 @@ import torch
 
 import oracle
 import synth
-from tests._util import rel_elem, rel_rows
+from tests._util import rel_elem, rel_fro, rel_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -150,3 +150,80 @@ def test_signed_rejected_on_wy_and_for_distance_output():
     with pytest.raises(L.HHError) as e:
         P.signed_raw("mahal", U, Xf, d_out=d, lam=d, Xb=Xf)
     assert e.value.status == L.HH_ERR_INVALID_ARG
+
+
+# ---------------------------------------------------------------------------
+# gradients (hh_backward_signed)
+
+GTOL = {"f64": 1e-10, "f32": 1e-5}
+BSHAPES = {"f64": [(100, 5, 333), (1000, 6, 257)],
+           "f32": [(100, 5, 333), (1000, 10, 257), (2048, 4, 130)]}
+
+
+def _bcases():
+    out = []
+    for t, shapes in BSHAPES.items():
+        for (n, h, N) in shapes:
+            for op in ("apply", "apply_T", "sym"):
+                for m in MODES:
+                    out.append((t, op, m, n, h, N))
+            out.append((t, "mahal", "in", n, h, N))
+    return out
+
+
+@pytest.mark.parametrize("t,op,mode,n,h,N", _bcases(), ids=lambda v: str(v))
+def test_signed_bwd_matches_oracle(t, op, mode, n, h, N):
+    dt = DT[t]
+    seed = 7 * n + h + N
+    U, lam, X, Xb = _inputs(t, n, h, N, seed)
+    d = _signs(n, seed)
+    dd = torch.tensor(d, dtype=dt, device=_dev())
+    din = dd if mode in ("in", "both") else None
+    dout = dd if mode in ("out", "both") else None
+    Uh, lh, Xh, Xbh = _host(U), _host(lam), _host(X), _host(Xb)
+    if op == "mahal":
+        w = torch.tensor(synth.gaussian(N, seed=seed, stream=synth.STREAM_W), dtype=dt, device=_dev())
+        dXa, dXb, dU, dl = P.signed_bwd_raw(op, U, X, w, d_in=din, lam=lam, Xb=Xb)
+        torch.cuda.synchronize()
+        r = oracle.signed_bwd(op, Uh, Xh, _host(w), d_in=d, lam=lh, Xb=Xbh)
+        assert rel_rows(_host(dXa), r[0]) < GTOL[t]
+        assert rel_rows(_host(dXb), r[1]) < GTOL[t]
+        assert rel_fro(_host(dU), r[2]) < GTOL[t]
+        assert rel_fro(_host(dl), r[3]) < GTOL[t]
+        return
+    G = torch.tensor(synth.gaussian((N, n), seed=seed, stream=synth.STREAM_G), dtype=dt, device=_dev())
+    dX, dU, dl = P.signed_bwd_raw(op, U, X, G, d_in=din, d_out=dout, lam=lam if op == "sym" else None)
+    torch.cuda.synchronize()
+    r = oracle.signed_bwd(op, Uh, Xh, _host(G), d_in=None if din is None else d,
+                          d_out=None if dout is None else d, lam=lh)
+    assert rel_rows(_host(dX), r[0]) < GTOL[t]
+    assert rel_fro(_host(dU), r[1]) < GTOL[t]
+    if op == "sym":
+        assert rel_fro(_host(dl), r[2]) < GTOL[t]
+
+
+@pytest.mark.parametrize("t", ["f64", "f32"])
+def test_signed_bwd_unit_diagonal_is_plain_bwd_bitwise(t):
+    dt = DT[t]
+    n, h, N = 1000, 6, 200
+    U, lam, X, Xb = _inputs(t, n, h, N, 8)
+    G = torch.tensor(synth.gaussian((N, n), seed=8, stream=synth.STREAM_G), dtype=dt, device=_dev())
+    one = torch.ones(n, dtype=dt, device=_dev())
+    a = P.signed_bwd_raw("sym", U, X, G, d_in=one, d_out=one, lam=lam)
+    b = P.sym_bwd_raw(U, lam, X, G)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    a = P.signed_bwd_raw("apply_T", U, X, G, d_in=one, d_out=one)
+    b = P.apply_bwd_raw(U, X, G, trans=True)
+    for x, y in zip(a[:2], b):
+        assert torch.equal(x, y)
+
+
+def test_signed_bwd_rejected_on_wy():
+    n, h, N = 256, 8, 32
+    U = torch.tensor(synth.reflectors(n, h, seed=1), dtype=torch.float32, device=_dev())
+    X = torch.zeros((N, n), dtype=torch.bfloat16, device=_dev())
+    d = torch.ones(n, dtype=torch.float32, device=_dev())
+    with pytest.raises(L.HHError) as e:
+        P.signed_bwd_raw("apply", U, X, X, d_out=d)
+    assert e.value.status == L.HH_ERR_UNSUPPORTED

@@ -443,3 +443,34 @@ def test_signed_identity_diagonal_reduces_to_plain_ops():
     assert np.array_equal(oracle.signed("apply_T", U, X, d_in=one, d_out=one), oracle.apply(U, X, trans=True))
     assert np.array_equal(oracle.signed("sym", U, X, d_in=one, d_out=one, lam=lam), oracle.sym(U, lam, X))
     assert np.array_equal(oracle.signed("mahal", U, X, d_in=one, lam=lam, Xb=Xb), oracle.mahal(U, lam, X, Xb))
+
+
+@pytest.mark.parametrize("op", ["apply", "apply_T", "sym", "mahal"])
+def test_signed_bwd_fd(op):
+    """The gradients with diagonals on either side against central differences
+    of the forward (eq. 1 / eq. thesbar placements, general diagonals so that a
+    dropped or misplaced factor shows)."""
+    rng = _rng(60 + len(op))
+    n, h, N = 7, 3, 4
+    U = rng.standard_normal((h, n)) * rng.uniform(0.5, 2.0, (h, 1))
+    X, Xb = rng.standard_normal((N, n)), rng.standard_normal((N, n))
+    lam = rng.uniform(0.1, 5.0, n)
+    din, dout = rng.uniform(0.5, 2.0, n), rng.uniform(0.5, 2.0, n)
+    if op == "mahal":
+        w = rng.standard_normal(N)
+        dXa, dXb, dU, dlam = oracle.signed_bwd(op, U, X, w, d_in=din, lam=lam, Xb=Xb)
+        L = lambda U_, lam_, Xa_, Xb_: np.sum(w * oracle.signed(op, U_, Xa_, d_in=din, lam=lam_, Xb=Xb_))
+        assert _rel(dXa, _fd(lambda P: L(U, lam, P, Xb), X)) < 1e-6
+        assert _rel(dXb, _fd(lambda P: L(U, lam, X, P), Xb)) < 1e-6
+        assert _rel(dU, _fd(lambda P: L(P, lam, X, Xb), U)) < 1e-6
+        assert _rel(dlam, _fd(lambda P: L(U, P, X, Xb), lam)) < 1e-6
+        return
+    G = rng.standard_normal((N, n))
+    dX, dU, dlam = oracle.signed_bwd(op, U, X, G, d_in=din, d_out=dout, lam=lam)
+    L = lambda U_, lam_, X_: np.sum(G * oracle.signed(op, U_, X_, d_in=din, d_out=dout, lam=lam_))
+    assert _rel(dX, _fd(lambda P: L(U, lam, P), X)) < 1e-6
+    assert _rel(dU, _fd(lambda P: L(P, lam, X), U)) < 1e-6
+    if op == "sym":
+        assert _rel(dlam, _fd(lambda P: L(U, P, X), lam)) < 1e-6
+    else:
+        assert dlam is None
