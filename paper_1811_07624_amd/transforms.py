@@ -373,6 +373,34 @@ class _Mahal(torch.autograd.Function):
                 dXb if ctx.needs_input_grad[3] else None, None, None)
 
 
+class _Signed(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, op, U, X, d_in, d_out, lam, Xb, compute, algo):
+        ctx.cfg = (op, compute, algo)
+        ctx.save_for_backward(U, X, d_in, d_out, lam, Xb)
+        return signed_raw(op, U, X, d_in, d_out, lam, Xb, compute, algo)
+
+    @staticmethod
+    def backward(ctx, dY):
+        U, X, d_in, d_out, lam, Xb = ctx.saved_tensors
+        op, compute, algo = ctx.cfg
+        r = signed_bwd_raw(op, U, X, dY.contiguous(), d_in, d_out, lam, Xb, compute, algo)
+        if op == "mahal":
+            dX, dXb, dU, dlam = r
+        else:
+            (dX, dU, dlam), dXb = r, None
+        dU = dU.to(U.dtype)
+        if dlam is not None and lam is not None:
+            dlam = dlam.to(lam.dtype)
+        return (None, dU, dX, None, None, dlam if lam is not None else None, dXb, None, None)
+
+
+def signed(op, U, X, *, d_in=None, d_out=None, lam=None, Xb=None, compute=None, algo="auto"):
+    """diag(d_out) op(diag(d_in) X) with gradients to U, X, lam and Xb (the
+    diagonals are fixed signs, not differentiated); op as in signed_raw."""
+    return _Signed.apply(op, U, X, d_in, d_out, lam, Xb, compute, algo)
+
+
 def apply(U, X, *, compute=None, algo="auto"):
     """Y = Q X with Q = H_1 ... H_h (rows of the result are Q x_j)."""
     return _Apply.apply(U, X, False, compute, algo)

@@ -227,3 +227,37 @@ def test_signed_bwd_rejected_on_wy():
     with pytest.raises(L.HHError) as e:
         P.signed_bwd_raw("apply", U, X, X, d_out=d)
     assert e.value.status == L.HH_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("op", ["apply", "apply_T", "sym", "mahal"])
+def test_signed_autograd(op):
+    """torch autograd through the signed forward gives the oracle's gradients."""
+    t, n, h, N = "f64", 200, 5, 60
+    dt = DT[t]
+    U, lam, X, Xb = _inputs(t, n, h, N, 21)
+    d = _signs(n, 21)
+    dd = torch.tensor(d, dtype=dt, device=_dev())
+    U.requires_grad_(True)
+    X.requires_grad_(True)
+    lam.requires_grad_(op in ("sym", "mahal"))
+    Xb.requires_grad_(op == "mahal")
+    dout = None if op == "mahal" else dd
+    Y = P.signed(op, U, X, d_in=dd, d_out=dout, lam=lam if op in ("sym", "mahal") else None,
+                 Xb=Xb if op == "mahal" else None)
+    if op == "mahal":
+        w = torch.tensor(synth.gaussian(N, seed=21, stream=synth.STREAM_W), dtype=dt, device=_dev())
+    else:
+        w = torch.tensor(synth.gaussian((N, n), seed=21, stream=synth.STREAM_G), dtype=dt, device=_dev())
+    (Y * w).sum().backward()
+    r = oracle.signed_bwd(op, _host(U), _host(X), _host(w), d_in=d, d_out=None if dout is None else d,
+                          lam=_host(lam), Xb=_host(Xb))
+    if op == "mahal":
+        assert rel_rows(_host(X.grad), r[0]) < GTOL[t]
+        assert rel_rows(_host(Xb.grad), r[1]) < GTOL[t]
+        assert rel_fro(_host(U.grad), r[2]) < GTOL[t]
+        assert rel_fro(_host(lam.grad), r[3]) < GTOL[t]
+    else:
+        assert rel_rows(_host(X.grad), r[0]) < GTOL[t]
+        assert rel_fro(_host(U.grad), r[1]) < GTOL[t]
+        if op == "sym":
+            assert rel_fro(_host(lam.grad), r[2]) < GTOL[t]
