@@ -261,3 +261,24 @@ def test_signed_autograd(op):
         assert rel_fro(_host(U.grad), r[1]) < GTOL[t]
         if op == "sym":
             assert rel_fro(_host(lam.grad), r[2]) < GTOL[t]
+
+
+@pytest.mark.parametrize("t", ["f64", "f32"])
+def test_signed_edge_cases(t):
+    """h = 0 leaves only the diagonals (exact products); an empty batch gives
+    zero dU and dlam."""
+    dt = DT[t]
+    n, N = 129, 37
+    rng = synth.host_rng(31, 13)
+    a = torch.tensor(rng.uniform(0.5, 2.0, n), dtype=dt, device=_dev())
+    b = torch.tensor(rng.uniform(0.5, 2.0, n), dtype=dt, device=_dev())
+    X = torch.tensor(synth.gaussian((N, n), seed=31), dtype=dt, device=_dev())
+    U0 = torch.empty((0, n), dtype=dt, device=_dev())
+    lam = torch.tensor(synth.eig_uniform(n, seed=31), dtype=dt, device=_dev())
+    assert torch.equal(P.signed_raw("apply", U0, X, d_in=a, d_out=b), X * a * b)
+    assert torch.equal(P.signed_raw("sym", U0, X, d_in=a, d_out=b, lam=lam), X * a * lam * b)
+    U = torch.tensor(synth.reflectors(n, 4, seed=31), dtype=dt, device=_dev())
+    E = torch.empty((0, n), dtype=dt, device=_dev())
+    dX, dU, dl = P.signed_bwd_raw("sym", U, E, E, d_in=a, d_out=b, lam=lam)
+    torch.cuda.synchronize()
+    assert dX.shape == (0, n) and torch.count_nonzero(dU) == 0 and torch.count_nonzero(dl) == 0
