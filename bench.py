@@ -40,6 +40,9 @@ WORKLOADS = {
                            "Q X, n=4096, h=64, N=2^18; fused sequential FP32"),
     "sym_n1024_h10": ("sym", 1024, 10, 1 << 20, "f32",
                       "Q diag(lam) Q^T X, n=1024, h=10, N=2^20; fused FP32"),
+    "sym_d_n1024_h10": ("sym_d", 1024, 10, 1 << 20, "f32",
+                        "D Q diag(lam) Q^T D X (eq. thesbar with a random sign diagonal D), n=1024, "
+                        "h=10, N=2^20; fused FP32"),
     "mahal_n512_h9": ("mahal", 512, 9, 1 << 22, "f32",
                       "Mahalanobis distances, n=512, h=9, N=2^22 pairs; fused FP32"),
     "mahal_fb_n512_h9": ("mahal_fb", 512, 9, 1 << 22, "f32",
@@ -78,6 +81,8 @@ def algorithmic(op, n, h, N, io_bytes, param_bytes=4):
         return 2 * n * io_bytes * N, 4 * n * h * N
     if op == "sym":
         return 2 * n * io_bytes * N, (8 * h + 1) * n * N
+    if op == "sym_d":      # the two diagonal products: 2n more
+        return 2 * n * io_bytes * N, (8 * h + 3) * n * N
     if op == "mahal":
         return (2 * n * io_bytes + param_bytes) * N, (4 * h + 3) * n * N
     if op == "apply_fb":   # forward: X in, Y out; backward: X, dY in, dX out
@@ -148,7 +153,10 @@ def main():
     Gd = None
     if op in ("apply_fb", "sym_fb"):
         Gd = synth.device_gaussian((N, n), seed=0, stream=synth.STREAM_G, device=dev, dtype=io_dt)
-    Y = torch.empty_like(X) if op in ("apply", "sym", "copy", "apply_fb", "sym_fb") else None
+    Y = torch.empty_like(X) if op in ("apply", "sym", "sym_d", "copy", "apply_fb", "sym_fb") else None
+    dsig = None
+    if op == "sym_d":
+        dsig = torch.tensor(np.where(synth.host_rng(0, 11).random(n) < 0.5, -1.0, 1.0), dtype=pdt, device=dev)
     torch.cuda.synchronize()
 
     def step():
@@ -158,6 +166,8 @@ def main():
             P.apply_raw(U, X, compute=tdt, out=Y)
         elif op == "sym":
             P.sym_raw(U, lam, X, compute=tdt, out=Y)
+        elif op == "sym_d":
+            P.signed_raw("sym", U, X, d_in=dsig, d_out=dsig, lam=lam, compute=tdt, out=Y)
         elif op == "mahal":
             P.mahal_raw(U, lam, X, Xb)
         elif op == "apply_fb":  # the forward keeps its WY coefficients for the backward
@@ -192,7 +202,7 @@ def main():
     # kernels (normalisation, T), so the same call on a single vector is timed
     # the same way and subtracted (its main kernel is one tile, a few us).
     ms_setup = 0.0
-    if op in ("apply", "sym", "mahal"):
+    if op in ("apply", "sym", "sym_d", "mahal"):
         X1 = X[:1]
         Y1 = Y[:1] if Y is not None else None
         Xb1 = Xb[:1] if Xb is not None else None
@@ -202,6 +212,8 @@ def main():
                 P.apply_raw(U, X1, compute=tdt, out=Y1)
             elif op == "sym":
                 P.sym_raw(U, lam, X1, compute=tdt, out=Y1)
+            elif op == "sym_d":
+                P.signed_raw("sym", U, X1, d_in=dsig, d_out=dsig, lam=lam, compute=tdt, out=Y1)
             else:
                 P.mahal_raw(U, lam, X1, Xb1)
         for _ in range(2):
@@ -324,17 +336,20 @@ def main():
         out["cpu_baseline"] = {"value": S / tcpu, "unit": "vectors/s (forward + backward)",
                                "cores": oracle.num_threads(), "kind": "oracle",
                                "sample": f"first {S} of {N} vectors of the same batch, FP64"}
-    if not args.no_cpu and op in ("apply", "sym", "mahal", "mahal_fb"):
+    if not args.no_cpu and op in ("apply", "sym", "sym_d", "mahal", "mahal_fb"):
         import oracle
         Uh = U.double().cpu().numpy()
         lh = lam.double().cpu().numpy()
         S = min(N, 64)
         Xs = X[:S].double().cpu().numpy()
         t = time.perf_counter()
+        dh = dsig.double().cpu().numpy() if dsig is not None else None
         if op == "apply":
             ref = oracle.apply(Uh, Xs)
         elif op == "sym":
             ref = oracle.sym(Uh, lh, Xs)
+        elif op == "sym_d":
+            ref = oracle.signed("sym", Uh, Xs, d_in=dh, d_out=dh, lam=lh)
         else:
             ref = oracle.mahal(Uh, lh, Xs, Xb[:S].double().cpu().numpy())
         t1 = time.perf_counter() - t
@@ -346,6 +361,8 @@ def main():
             oracle.apply(Uh, Xs2)
         elif op == "sym":
             oracle.sym(Uh, lh, Xs2)
+        elif op == "sym_d":
+            oracle.signed("sym", Uh, Xs2, d_in=dh, d_out=dh, lam=lh)
         elif op == "mahal":
             oracle.mahal(Uh, lh, Xs2, Xb[:S2].double().cpu().numpy())
         else:
@@ -356,9 +373,11 @@ def main():
         out["cpu_baseline"] = {"value": S2 / tcpu, "unit": "vectors/s",
                                "cores": oracle.num_threads(), "kind": "oracle",
                                "sample": f"first {S2} of {N} vectors of the same batch, FP64"}
-        if op in ("apply", "sym"):
+        if op in ("apply", "sym", "sym_d"):
             Yg = (P.apply_raw(U, X[:S], compute=tdt) if op == "apply" else
-                  P.sym_raw(U, lam, X[:S], compute=tdt)).double().cpu().numpy()
+                  P.sym_raw(U, lam, X[:S], compute=tdt) if op == "sym" else
+                  P.signed_raw("sym", U, X[:S], d_in=dsig, d_out=dsig, lam=lam, compute=tdt)
+                  ).double().cpu().numpy()
             err = float(np.max(np.linalg.norm(Yg - ref, axis=1) / np.linalg.norm(ref, axis=1)))
         else:
             dg = P.mahal_raw(U, lam, X[:S], Xb[:S]).double().cpu().numpy()
