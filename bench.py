@@ -121,6 +121,25 @@ def measured_traffic(kernel_key, src_paths):
         return None
 
 
+def orthogonality(P, U, n, tdt, dev):
+    """||Q^T Q - I||_F / sqrt(n) and max |(Q^T Q - I)_ij| of the path's Q and
+    Q^T, each column of Q being the path applied to a unit vector."""
+    import torch
+    res = {}
+    eye = torch.eye(n, dtype=torch.float64, device=dev)
+    for trans in (False, True):
+        Qt = P.apply_raw(U, eye.to(tdt), trans=trans, compute=tdt).double()
+        E = Qt @ Qt.T - eye
+        res["QT" if trans else "Q"] = {"fro_over_sqrt_n": float(E.norm()) / math.sqrt(n),
+                                        "max_abs": float(E.abs().max())}
+        del Qt, E
+    res["fro_over_sqrt_n"] = max(r["fro_over_sqrt_n"] for r in (res["Q"], res["QT"]))
+    res["max_abs"] = max(r["max_abs"] for r in (res["Q"], res["QT"]))
+    del eye
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -277,6 +296,12 @@ def main():
                      "setup_ms_events": ms_setup, "algorithmic_bytes": abytes,
                      "algorithmic_flops": aflops},
     }
+
+    # orthogonality of the operator the path applies: Q (and Q^T) applied to
+    # the identity (exact in every compute type) at this workload's n and h,
+    # with the same arithmetic; E = Q^T Q - I formed in FP64
+    if op != "copy":
+        out["orth"] = orthogonality(P, U, n, tdt, dev)
 
     # the fused FP32 kernel on the same Q X shape, timed beside the headline
     if args.workload == DEFAULT and not args.no_compare:

@@ -2,9 +2,11 @@
 
 TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
 benchmark's CPU-baseline leg, never by the product package.  It shares no code
-with the HIP implementation; the arithmetic lives in ``hh_oracle.c`` (plain C,
-double precision, straightforward loops) and this module only marshals numpy
-arrays through ctypes.
+with the HIP implementation.  The reflector arithmetic lives in
+``hh_oracle.c`` (plain C, double precision, straightforward loops) and is
+reached through ctypes; the only arithmetic in this module is the elementwise
+diagonal products of ``signed`` / ``signed_bwd`` (numpy, FP64), written out as
+the products of diagonal matrices they are.
 
 Array conventions (numpy, C-contiguous float64):
   U   : (h, n)  row k is the reflector vector u_k  (column k of the n x h matrix)

@@ -255,10 +255,12 @@ def mahal_bwd_raw(U, lam, Xa, Xb, dd, compute=None, algo="auto", need_dX=True, n
 
 
 def signed_bwd_raw(op, U, X, dY, d_in=None, d_out=None, lam=None, Xb=None, compute=None,
-                   algo="auto"):
+                   algo="auto", need_dX=True, need_dU=True, need_dlam=True):
     """Gradients of <dY, signed_raw(op, U, X, d_in, d_out, lam, Xb)>: returns
     (dX, dU, dlam) for "apply", "apply_T" and "sym" (dlam None unless "sym"),
-    (dXa, dXb, dU, dlam) for "mahal" (dY = the N distance weights)."""
+    (dXa, dXb, dU, dlam) for "mahal" (dY = the N distance weights).  A
+    gradient whose need_* flag is False is neither computed nor allocated
+    (None is returned in its place)."""
     ops = {"apply": L.HH_OP_APPLY_BWD, "apply_T": L.HH_OP_APPLY_T_BWD, "sym": L.HH_OP_SYM_BWD,
            "mahal": L.HH_OP_MAHAL_BWD}
     hop = ops[op]
@@ -280,19 +282,20 @@ def signed_bwd_raw(op, U, X, dY, d_in=None, d_out=None, lam=None, Xb=None, compu
         dY = _param(dY, param)
         lddy, ldb = 0, L.ld(Xb)
     else:
-        dY = _rows(dY)
+        dY = _rows(dY.to(X.dtype))
         lddy, ldb = L.ld(dY), 0
     desc = L.make_desc(n, h, N, param, io, comp, algo)
-    dX = torch.empty((N, n), dtype=io, device=X.device)
-    dXb = torch.empty((N, n), dtype=io, device=X.device) if mahal else None
-    dU = torch.empty((h, n), dtype=param, device=X.device)
-    dlam = torch.empty((n,), dtype=param, device=X.device) if hop in (L.HH_OP_SYM_BWD, L.HH_OP_MAHAL_BWD) else None
+    dX = torch.empty((N, n), dtype=io, device=X.device) if need_dX else None
+    dXb = torch.empty((N, n), dtype=io, device=X.device) if (mahal and need_dX) else None
+    dU = torch.empty((h, n), dtype=param, device=X.device) if need_dU else None
+    has_lam = hop in (L.HH_OP_SYM_BWD, L.HH_OP_MAHAL_BWD)
+    dlam = torch.empty((n,), dtype=param, device=X.device) if (has_lam and need_dlam) else None
     ws = L.workspace(hop, desc, X.device)
     L.check("hh_backward_signed", L.lib().hh_backward_signed(
         hop, ctypes.byref(desc), L.ptr(U), max(n, U.stride(0) if h else n), L.ptr(lam),
         L.ptr(d_in), L.ptr(d_out), L.ptr(X), L.ld(X), L.ptr(Xb), ldb, L.ptr(dY), lddy,
-        L.ptr(dX), L.ptr(dXb), n, L.ptr(dU), n, L.ptr(dlam), L.ptr(ws), ws.numel(),
-        L.stream_of(X)))
+        L.ptr(dX), L.ptr(dXb), n if dX is None else L.ld(dX), L.ptr(dU), n, L.ptr(dlam),
+        L.ptr(ws), ws.numel(), L.stream_of(X)))
     return (dX, dXb, dU, dlam) if mahal else (dX, dU, dlam)
 
 
@@ -384,20 +387,29 @@ class _Signed(torch.autograd.Function):
     def backward(ctx, dY):
         U, X, d_in, d_out, lam, Xb = ctx.saved_tensors
         op, compute, algo = ctx.cfg
-        r = signed_bwd_raw(op, U, X, dY.contiguous(), d_in, d_out, lam, Xb, compute, algo)
+        need = ctx.needs_input_grad  # (op, U, X, d_in, d_out, lam, Xb, compute, algo)
+        r = signed_bwd_raw(op, U, X, dY.contiguous(), d_in, d_out, lam, Xb, compute, algo,
+                           need_dX=need[2] or need[6], need_dU=need[1],
+                           need_dlam=lam is not None and need[5])
         if op == "mahal":
             dX, dXb, dU, dlam = r
         else:
             (dX, dU, dlam), dXb = r, None
-        dU = dU.to(U.dtype)
-        if dlam is not None and lam is not None:
+        if dU is not None:
+            dU = dU.to(U.dtype)
+        if dlam is not None:
             dlam = dlam.to(lam.dtype)
-        return (None, dU, dX, None, None, dlam if lam is not None else None, dXb, None, None)
+        return (None, dU, dX if need[2] else None, None, None, dlam,
+                dXb if need[6] else None, None, None)
 
 
 def signed(op, U, X, *, d_in=None, d_out=None, lam=None, Xb=None, compute=None, algo="auto"):
     """diag(d_out) op(diag(d_in) X) with gradients to U, X, lam and Xb (the
-    diagonals are fixed signs, not differentiated); op as in signed_raw."""
+    diagonals are fixed signs, not differentiated: a diagonal that requires a
+    gradient is rejected); op as in signed_raw."""
+    for name, t in (("d_in", d_in), ("d_out", d_out)):
+        if t is not None and t.requires_grad:
+            raise ValueError(f"{name} is a fixed diagonal and has no gradient; pass {name}.detach()")
     return _Signed.apply(op, U, X, d_in, d_out, lam, Xb, compute, algo)
 
 

@@ -34,3 +34,20 @@ def gpu_available():
         return torch.cuda.is_available()
     except Exception:
         return False
+
+
+def rel_refl(dU, ref):
+    """Per-reflector relative error of a gradient laid out (h, n): the max
+    over reflectors k of ||dU_k - ref_k|| / ||ref_k||.  A reflector whose
+    reference gradient is exactly zero (a zero column) contributes
+    ||dU_k|| / ||ref||_F instead.  A wrong gradient for one reflector cannot
+    hide behind the others here, as it can in a whole-tensor norm."""
+    A = np.asarray(dU, dtype=np.float64)
+    R = np.asarray(ref, dtype=np.float64)
+    if A.size == 0:
+        return 0.0
+    num = np.linalg.norm(A - R, axis=-1)
+    den = np.linalg.norm(R, axis=-1)
+    tot = max(float(np.linalg.norm(R)), 1e-300)
+    out = np.where(den > 0, num / np.maximum(den, 1e-300), num / tot)
+    return float(np.max(out))

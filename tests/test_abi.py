@@ -228,3 +228,16 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
 def test_version():
     v = P.lib().hh_version()
     assert v >= 300 and v < 10000  # 0.x.y with the saved record, FP32 data on the WY path and diagonals
+
+
+def test_signed_rejects_differentiable_diagonal():
+    """The diagonals of P.signed are fixed signs: one that requires a gradient
+    is refused before anything runs (it would otherwise get none silently)."""
+    import torch
+    U = torch.zeros((2, 8))
+    X = torch.zeros((4, 8))
+    d = torch.ones(8, requires_grad=True)
+    with pytest.raises(ValueError, match="fixed diagonal"):
+        P.signed("apply", U, X, d_in=d)
+    with pytest.raises(ValueError, match="fixed diagonal"):
+        P.signed("apply", U, X, d_out=d)

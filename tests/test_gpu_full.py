@@ -17,7 +17,7 @@ import torch
 
 import oracle
 import synth
-from tests._util import rel_elem, rel_fro, rel_rows
+from tests._util import rel_elem, rel_fro, rel_rows, rel_refl
 
 pytestmark = pytest.mark.gpu
 
@@ -89,6 +89,7 @@ def test_full_mahal_fused_fp32_fwd_bwd():
     _, _, dU, dlam = P.mahal_bwd_raw(U, lam, Xa, Xb, w, need_dX=False)
     _, _, rdU, rdlam = oracle.mahal_bwd(Uh, lh, xa, xb, host(w[idx]))
     assert rel_fro(host(dU), rdU) < TOL32
+    assert rel_refl(host(dU), rdU) < TOL32, rel_refl(host(dU), rdU)
     assert rel_fro(host(dlam), rdlam) < TOL32
     del Xa, Xb
     release()
@@ -116,6 +117,7 @@ def test_full_qx_wy_bf16_fwd_bwd():
     rdX, rdU = oracle.apply_bwd(Uh, xs, host(G[idx]))
     assert rel_rows(host(dX[idx]), rdX) < TOL16
     assert rel_fro(host(dU), rdU) < TOL16
+    assert rel_refl(host(dU), rdU) < TOL16, rel_refl(host(dU), rdU)
     # dX = Q^T G: rows with G = 0 are exactly zero
     mask = torch.ones(N, dtype=torch.bool, device=dev())
     mask[idx] = False
@@ -142,6 +144,7 @@ def test_full_sym_wy_fp16_fwd_bwd():
     rdX, rdU, rdlam = oracle.sym_bwd(Uh, lh, xs, host(G[idx]))
     assert rel_rows(host(dX[idx]), rdX) < TOL16
     assert rel_fro(host(dU), rdU) < TOL16
+    assert rel_refl(host(dU), rdU) < TOL16, rel_refl(host(dU), rdU)
     assert rel_fro(host(dlam), rdlam) < TOL16
     del X, G, dX, rec
     release()

@@ -16,7 +16,7 @@ import torch
 
 import oracle
 import synth
-from tests._util import rel_elem, rel_fro, rel_rows
+from tests._util import rel_elem, rel_fro, rel_rows, rel_refl
 
 pytestmark = pytest.mark.gpu
 
@@ -86,6 +86,7 @@ def test_random_shape(algo, tname, op, n, h, N, seed):
             assert rel_rows(_host(dX), rdX) < gtol
             if N > 0 and h > 0:
                 assert rel_fro(_host(dU), rdU) < gtol
+                assert rel_refl(_host(dU), rdU) < gtol, rel_refl(_host(dU), rdU)
         elif op == "sym":
             Y = P.sym_raw(U, lam, X, compute=dt)
             dX, dU, dl = P.sym_bwd_raw(U, lam, X, G, compute=dt)
@@ -97,6 +98,7 @@ def test_random_shape(algo, tname, op, n, h, N, seed):
                 assert rel_fro(_host(dl), rdl) < gtol
                 if h > 0:
                     assert rel_fro(_host(dU), rdU) < gtol
+                    assert rel_refl(_host(dU), rdU) < gtol, rel_refl(_host(dU), rdU)
         else:
             Xb = torch.tensor(synth.gaussian((N, n), seed=seed, stream=synth.STREAM_XB), dtype=dt,
                               device=_dev())
@@ -112,6 +114,7 @@ def test_random_shape(algo, tname, op, n, h, N, seed):
                 assert rel_fro(_host(dl), rdl) < gtol
                 if h > 0:
                     assert rel_fro(_host(dU), rdU) < gtol
+                    assert rel_refl(_host(dU), rdU) < gtol, rel_refl(_host(dU), rdU)
     except L.HHError as e:
         if _unsupported(e):
             pytest.skip(f"unsupported by the library: {e}")

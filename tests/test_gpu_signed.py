@@ -14,7 +14,7 @@ import torch
 
 import oracle
 import synth
-from tests._util import rel_elem, rel_fro, rel_rows
+from tests._util import rel_elem, rel_fro, rel_rows, rel_refl
 
 pytestmark = pytest.mark.gpu
 
@@ -189,6 +189,7 @@ def test_signed_bwd_matches_oracle(t, op, mode, n, h, N):
         assert rel_rows(_host(dXa), r[0]) < GTOL[t]
         assert rel_rows(_host(dXb), r[1]) < GTOL[t]
         assert rel_fro(_host(dU), r[2]) < GTOL[t]
+        assert rel_refl(_host(dU), r[2]) < GTOL[t], rel_refl(_host(dU), r[2])
         assert rel_fro(_host(dl), r[3]) < GTOL[t]
         return
     G = torch.tensor(synth.gaussian((N, n), seed=seed, stream=synth.STREAM_G), dtype=dt, device=_dev())
@@ -198,6 +199,7 @@ def test_signed_bwd_matches_oracle(t, op, mode, n, h, N):
                           d_out=None if dout is None else d, lam=lh)
     assert rel_rows(_host(dX), r[0]) < GTOL[t]
     assert rel_fro(_host(dU), r[1]) < GTOL[t]
+    assert rel_refl(_host(dU), r[1]) < GTOL[t], rel_refl(_host(dU), r[1])
     if op == "sym":
         assert rel_fro(_host(dl), r[2]) < GTOL[t]
 
@@ -255,10 +257,12 @@ def test_signed_autograd(op):
         assert rel_rows(_host(X.grad), r[0]) < GTOL[t]
         assert rel_rows(_host(Xb.grad), r[1]) < GTOL[t]
         assert rel_fro(_host(U.grad), r[2]) < GTOL[t]
+        assert rel_refl(_host(U.grad), r[2]) < GTOL[t], rel_refl(_host(U.grad), r[2])
         assert rel_fro(_host(lam.grad), r[3]) < GTOL[t]
     else:
         assert rel_rows(_host(X.grad), r[0]) < GTOL[t]
         assert rel_fro(_host(U.grad), r[1]) < GTOL[t]
+        assert rel_refl(_host(U.grad), r[1]) < GTOL[t], rel_refl(_host(U.grad), r[1])
         if op == "sym":
             assert rel_fro(_host(lam.grad), r[2]) < GTOL[t]
 
@@ -282,3 +286,27 @@ def test_signed_edge_cases(t):
     dX, dU, dl = P.signed_bwd_raw("sym", U, E, E, d_in=a, d_out=b, lam=lam)
     torch.cuda.synchronize()
     assert dX.shape == (0, n) and torch.count_nonzero(dU) == 0 and torch.count_nonzero(dl) == 0
+
+
+@pytest.mark.parametrize("op", ["apply", "sym", "mahal"])
+def test_signed_autograd_only_needed_grads(op):
+    """Only the gradients autograd asks for are computed: with just U
+    requiring a gradient, dU matches the full backward's and X gets none."""
+    t = "f32"
+    dt = DT[t]
+    n, h, N = 300, 5, 64
+    U, lam, X, Xb = _inputs(t, n, h, N, 21)
+    d = torch.tensor(_signs(n, 21), dtype=dt, device=_dev())
+    Ug = U.clone().requires_grad_(True)
+    kw = dict(d_in=d, lam=lam if op in ("sym", "mahal") else None, Xb=Xb if op == "mahal" else None)
+    if op != "mahal":
+        kw["d_out"] = d
+    Y = P.signed(op, Ug, X, **kw)
+    G = torch.tensor(synth.gaussian(tuple(Y.shape), seed=21, stream=synth.STREAM_G), dtype=dt,
+                     device=_dev())
+    (Y * G).sum().backward()
+    full = P.signed_bwd_raw(op, U, X, G, **kw)
+    dU_full = full[2] if op == "mahal" else full[1]
+    torch.cuda.synchronize()
+    assert X.grad is None
+    assert rel_fro(_host(Ug.grad), _host(dU_full)) < 1e-6
