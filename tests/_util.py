@@ -38,16 +38,19 @@ def gpu_available():
 
 def rel_refl(dU, ref):
     """Per-reflector relative error of a gradient laid out (h, n): the max
-    over reflectors k of ||dU_k - ref_k|| / ||ref_k||.  A reflector whose
-    reference gradient is exactly zero (a zero column) contributes
-    ||dU_k|| / ||ref||_F instead.  A wrong gradient for one reflector cannot
-    hide behind the others here, as it can in a whole-tensor norm."""
+    over reflectors k of ||dU_k - ref_k|| / max(||ref_k||, rms_k ||ref_k||).
+    Measured against the reflector's own gradient, floored at the rms
+    reflector-gradient norm: rounding errors of the shared products scale
+    with the typical gradient, so a reflector whose gradient is unusually
+    small (or exactly zero, a zero column) is not held to a tighter absolute
+    bound than the others, while a wrong gradient for one reflector (an error
+    of the size of its gradient) still fails, as it might not in a
+    whole-tensor norm."""
     A = np.asarray(dU, dtype=np.float64)
     R = np.asarray(ref, dtype=np.float64)
     if A.size == 0:
         return 0.0
     num = np.linalg.norm(A - R, axis=-1)
     den = np.linalg.norm(R, axis=-1)
-    tot = max(float(np.linalg.norm(R)), 1e-300)
-    out = np.where(den > 0, num / np.maximum(den, 1e-300), num / tot)
-    return float(np.max(out))
+    rms = float(np.linalg.norm(R)) / np.sqrt(max(R.shape[0], 1))
+    return float(np.max(num / np.maximum(np.maximum(den, rms), 1e-300)))
