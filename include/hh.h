@@ -273,6 +273,35 @@ HH_API hh_status hh_backward_signed(hh_op op, const hh_desc *d, const void *U, i
                              int64_t lddx, void *dU, int64_t lddu, void *dlam, void *ws,
                              size_t ws_bytes, hipStream_t stream);
 
+/* Size of the static device scratch of hh_forward_noalloc (16 MiB, held by
+ * each GPU the library runs on until the process ends). */
+#define HH_NOALLOC_SCRATCH_BYTES (16u << 20)
+
+/* For callers that cannot allocate device memory or provide a workspace
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the forward ops of hh_apply (op = HH_OP_APPLY), hh_apply_T
+ * (HH_OP_APPLY_T), hh_sym_apply (HH_OP_SYM, lam) and hh_mahalanobis
+ * (HH_OP_MAHAL: X, ldx = Xa, lda; Xb, ldb; Y = dist, ldy ignored), same
+ * arguments and results, with the workspace taken from a static device array
+ * of HH_NOALLOC_SCRATCH_BYTES inside the library instead of an argument.  The
+ * caller still passes inputs and outputs.  Nothing is allocated (no hipMalloc,
+ * hipFree or allocating library call); the array's device address is looked
+ * up once per device on the first call there.  A call whose workspace
+ * (hh_workspace_size) exceeds HH_NOALLOC_SCRATCH_BYTES returns
+ * HH_ERR_WORKSPACE and enqueues nothing: 16-bit WY calls fit at every
+ * supported size (n <= 8192, h <= 128), FUSED calls while h * n * (4 or 8)
+ * bytes of padded reflectors fit, and WY calls with F32 data only while their
+ * 16-bit copies of X and Y fit.  The stream must belong to the current
+ * device (else HH_ERR_INVALID_ARG).  Every call on one GPU shares that GPU's
+ * array: calls that overlap in time on one GPU (different streams, or
+ * threads) race and give undefined results; calls ordered on one stream are
+ * safe.  The array keeps the last call's contents; no kernel of these ops
+ * reads scratch it has not written in the same call. */
+HH_API hh_status hh_forward_noalloc(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
+                                    const void *lam, const void *X, int64_t ldx,
+                                    const void *Xb, int64_t ldb, void *Y, int64_t ldy,
+                                    hipStream_t stream);
+
 /* Static text for a status code. */
 HH_API const char *hh_status_string(hh_status s);
 

@@ -24,8 +24,12 @@ EXPORTS = (
     "hh_workspace_size", "hh_apply", "hh_apply_T", "hh_sym_apply", "hh_mahalanobis",
     "hh_apply_backward", "hh_apply_T_backward", "hh_sym_apply_backward",
     "hh_mahalanobis_backward", "hh_saved_size", "hh_forward_save", "hh_backward_saved",
-    "hh_forward_signed", "hh_backward_signed", "hh_status_string", "hh_last_error", "hh_version",
+    "hh_forward_signed", "hh_backward_signed", "hh_forward_noalloc", "hh_status_string",
+    "hh_last_error", "hh_version",
 )
+
+# Bytes of the library's static scratch used by hh_forward_noalloc.
+NOALLOC_SCRATCH_BYTES = 16 << 20
 
 _TORCH_TO_HH = {torch.float64: HH_F64, torch.float32: HH_F32, torch.bfloat16: HH_BF16,
                 torch.float16: HH_F16}
@@ -73,6 +77,7 @@ def lib():
         "hh_forward_signed": [ctypes.c_int, D, P, I, P, P, P, P, I, P, I, P, I, P, S, P],
         "hh_backward_signed": [ctypes.c_int, D, P, I, P, P, P, P, I, P, I, P, I, P, P, I, P, I, P, P,
                                S, P],
+        "hh_forward_noalloc": [ctypes.c_int, D, P, I, P, P, I, P, I, P, I, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)

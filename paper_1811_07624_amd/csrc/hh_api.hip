@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "hh_internal.h"
@@ -319,11 +320,72 @@ static hh_status backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu
     return HH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of hh_forward_noalloc: a file-scope device array, one copy on each
+// GPU the library's code object is loaded on, held until the process ends.
+// In host code `scratch` names a host-side stand-in, not device memory: the
+// device address comes from hipGetSymbolAddress, once per device (with that
+// device current), and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[HH_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+static hh_status scratch_for(hipStream_t st, void **out) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    int dev = cur;
+    if (st) {
+        e = hipStreamGetDevice(st, &dev);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamGetDevice");
+    }
+    if (dev != cur)
+        return fail(HH_ERR_INVALID_ARG,
+                    "the stream belongs to device %d but device %d is current; make the stream's "
+                    "device current", dev, cur);
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(HH_ERR_UNSUPPORTED, "device index %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(HH_ERR_HIP, "hipGetSymbolAddress(scratch) gave a null address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HH_OK;
+}
+
 }  // namespace hh
 
 using namespace hh;
 
 extern "C" {
+
+hh_status hh_forward_noalloc(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
+                             const void *lam, const void *X, int64_t ldx, const void *Xb,
+                             int64_t ldb, void *Y, int64_t ldy, hipStream_t stream) {
+    if (op != HH_OP_APPLY && op != HH_OP_APPLY_T && op != HH_OP_SYM && op != HH_OP_MAHAL)
+        return fail(HH_ERR_INVALID_ARG, "op must be a forward op");
+    Algo algo;
+    HH_TRY(check_desc(d, &algo));
+    size_t need = 0;
+    HH_TRY(hh_workspace_size(op, d, &need));
+    if (need > (size_t)HH_NOALLOC_SCRATCH_BYTES)
+        return fail(HH_ERR_WORKSPACE,
+                    "this call needs %zu bytes of scratch; the library's static scratch holds %zu "
+                    "(use the entry point with a workspace argument)",
+                    need, (size_t)HH_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    HH_TRY(scratch_for(stream, &ws));
+    const bool two = op == HH_OP_MAHAL;
+    return forward(op, d, U, ldu, (op == HH_OP_SYM || two) ? lam : nullptr, X, ldx,
+                   two ? Xb : nullptr, two ? ldb : 0, Y, two ? 0 : ldy, ws,
+                   (size_t)HH_NOALLOC_SCRATCH_BYTES, stream);
+}
 
 hh_status hh_workspace_size(hh_op op, const hh_desc *d, size_t *bytes) {
     if (!bytes) return fail(HH_ERR_INVALID_ARG, "bytes must not be null");
@@ -480,6 +542,6 @@ const char *hh_status_string(hh_status s) {
 
 const char *hh_last_error(void) { return g_last_error.c_str(); }
 
-int hh_version(void) { return 300; }  // 0.3.0: diagonals on either side (hh_forward_signed, hh_backward_signed)
+int hh_version(void) { return 400; }  // 0.4.0: allocation-free forward (hh_forward_noalloc)
 
 }  // extern "C"

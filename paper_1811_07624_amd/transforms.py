@@ -174,6 +174,35 @@ def signed_raw(op, U, X, d_in=None, d_out=None, lam=None, Xb=None, compute=None,
     return Y
 
 
+def forward_noalloc_raw(op, U, X, lam=None, Xb=None, compute=None, algo="auto", out=None):
+    """The forward op ("apply", "apply_T", "sym" or "mahal") through
+    hh_forward_noalloc: no workspace is allocated (the library's static device
+    scratch is used; calls that overlap on one GPU race).  Only the output is
+    allocated here, unless ``out`` is given."""
+    ops = {"apply": L.HH_OP_APPLY, "apply_T": L.HH_OP_APPLY_T, "sym": L.HH_OP_SYM,
+           "mahal": L.HH_OP_MAHAL}
+    hop = ops[op]
+    _check_dev(U, X, *[t for t in (lam, Xb) if t is not None])
+    X = _rows(X)
+    param, io, comp = _cfg(X, compute)
+    U = _param(U, param)
+    lam = None if lam is None else _param(lam, param)
+    N, n = X.shape
+    h = U.shape[0]
+    desc = L.make_desc(n, h, N, param, io, comp, algo)
+    if hop == L.HH_OP_MAHAL:
+        Xb = _rows(Xb)
+        Y = torch.empty((N,), dtype=param, device=X.device) if out is None else out
+        ldy, ldb = 0, L.ld(Xb)
+    else:
+        Y = torch.empty((N, n), dtype=io, device=X.device) if out is None else out
+        ldy, ldb = L.ld(Y), 0
+    L.check("hh_forward_noalloc", L.lib().hh_forward_noalloc(
+        hop, ctypes.byref(desc), L.ptr(U), max(n, U.stride(0) if h else n), L.ptr(lam),
+        L.ptr(X), L.ld(X), L.ptr(Xb), ldb, L.ptr(Y), ldy, L.stream_of(X)))
+    return Y
+
+
 def apply_bwd_raw(U, X, dY, trans=False, compute=None, algo="auto", need_dX=True, need_dU=True,
                   saved=None):
     """Gradients of Y = Q X (or Q^T X); saved: the forward's record (WY only)."""

@@ -241,3 +241,21 @@ def test_signed_rejects_differentiable_diagonal():
         P.signed("apply", U, X, d_in=d)
     with pytest.raises(ValueError, match="fixed diagonal"):
         P.signed("apply", U, X, d_out=d)
+
+
+def test_noalloc_validation():
+    """hh_forward_noalloc refuses, on the host and before any device call,
+    backward ops, bad descriptors and calls whose workspace exceeds the static
+    scratch (fake pointers: nothing is dereferenced)."""
+    v = ctypes.c_void_p
+    lib = P.lib()
+
+    def call(op, desc):
+        return lib.hh_forward_noalloc(op, ctypes.byref(desc), v(1024), desc.n, v(6144), v(2048),
+                                      desc.n, v(4096), desc.n, v(3072), desc.n, None)
+    assert call(L.HH_OP_APPLY_BWD, _desc()) == L.HH_ERR_INVALID_ARG
+    assert call(L.HH_OP_APPLY, _desc(n=0)) == L.HH_ERR_INVALID_ARG
+    assert call(L.HH_OP_MAHAL, _wy_desc()) == L.HH_ERR_UNSUPPORTED
+    big = L.HHDesc(4096, 64, 4096, L.HH_F32, L.HH_F32, L.HH_BF16, L.HH_ALGO_AUTO)  # 64 MiB copies
+    assert call(L.HH_OP_APPLY, big) == L.HH_ERR_WORKSPACE
+    assert b"static scratch" in lib.hh_last_error()
