@@ -55,7 +55,23 @@ static size_t dtype_size(hh_dtype t) {
     return 0;
 }
 
-static bool valid_dtype(hh_dtype t) { return t == HH_F64 || t == HH_F32 || t == HH_BF16 || t == HH_F16; }
+// An enum object holding a value outside its enumerators (a caller's bad
+// code) must not be read as that enum type: such a load is undefined in C++.
+// Codes are read as the int they are stored in and checked before use.
+template <typename E> static int raw_code(const E &e) {
+    static_assert(sizeof(E) == sizeof(int), "C enums are int-sized");
+    int v;
+    std::memcpy(&v, &e, sizeof v);
+    return v;
+}
+
+static bool valid_dtype(int t) { return t == HH_F64 || t == HH_F32 || t == HH_BF16 || t == HH_F16; }
+
+// True when op is one of the codes in [lo, hi].
+static bool op_in(const hh_op &op, int lo, int hi) {
+    const int v = raw_code(op);
+    return v >= lo && v <= hi;
+}
 
 // ---------------------------------------------------------------------------
 // Descriptor checks shared by every entry point.
@@ -68,8 +84,12 @@ static hh_status check_desc(const hh_desc *d, Algo *algo) {
     if (d->N < 0) return fail(HH_ERR_INVALID_ARG, "N = %lld must be >= 0", (long long)d->N);
     if (d->n > (int64_t)1 << 30 || d->h > (int64_t)1 << 30)
         return fail(HH_ERR_UNSUPPORTED, "n and h must be < 2^30");
-    if (!valid_dtype(d->param_dtype) || !valid_dtype(d->io_dtype) || !valid_dtype(d->compute_dtype))
+    if (!valid_dtype(raw_code(d->param_dtype)) || !valid_dtype(raw_code(d->io_dtype)) ||
+        !valid_dtype(raw_code(d->compute_dtype)))
         return fail(HH_ERR_INVALID_ARG, "unknown dtype code");
+    const int ac = raw_code(d->algo);
+    if (ac != HH_ALGO_AUTO && ac != HH_ALGO_FUSED && ac != HH_ALGO_WY)
+        return fail(HH_ERR_INVALID_ARG, "unknown algo code");
     hh_algo a = d->algo;
     if (a == HH_ALGO_AUTO)
         a = (d->compute_dtype == HH_F64 || d->compute_dtype == HH_F32) ? HH_ALGO_FUSED : HH_ALGO_WY;
@@ -368,7 +388,7 @@ extern "C" {
 hh_status hh_forward_noalloc(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
                              const void *lam, const void *X, int64_t ldx, const void *Xb,
                              int64_t ldb, void *Y, int64_t ldy, hipStream_t stream) {
-    if (op != HH_OP_APPLY && op != HH_OP_APPLY_T && op != HH_OP_SYM && op != HH_OP_MAHAL)
+    if (!op_in(op, HH_OP_APPLY, HH_OP_MAHAL))
         return fail(HH_ERR_INVALID_ARG, "op must be a forward op");
     Algo algo;
     HH_TRY(check_desc(d, &algo));
@@ -389,7 +409,7 @@ hh_status hh_forward_noalloc(hh_op op, const hh_desc *d, const void *U, int64_t 
 
 hh_status hh_workspace_size(hh_op op, const hh_desc *d, size_t *bytes) {
     if (!bytes) return fail(HH_ERR_INVALID_ARG, "bytes must not be null");
-    if ((int)op < HH_OP_APPLY || (int)op > HH_OP_MAHAL_BWD) return fail(HH_ERR_INVALID_ARG, "unknown op");
+    if (!op_in(op, HH_OP_APPLY, HH_OP_MAHAL_BWD)) return fail(HH_ERR_INVALID_ARG, "unknown op");
     Algo algo;
     HH_TRY(check_desc(d, &algo));
     if (algo == Algo::WY) return wy_workspace_size(op, d, bytes);
@@ -461,7 +481,7 @@ hh_status hh_mahalanobis_backward(const hh_desc *d, const void *U, int64_t ldu, 
 
 hh_status hh_saved_size(hh_op op, const hh_desc *d, size_t *bytes) {
     if (!bytes) return fail(HH_ERR_INVALID_ARG, "bytes must not be null");
-    if (op != HH_OP_APPLY && op != HH_OP_APPLY_T && op != HH_OP_SYM)
+    if (!op_in(op, HH_OP_APPLY, HH_OP_SYM))
         return fail(HH_ERR_INVALID_ARG, "op must be HH_OP_APPLY, HH_OP_APPLY_T or HH_OP_SYM");
     Algo algo;
     HH_TRY(check_desc(d, &algo));
@@ -472,7 +492,7 @@ hh_status hh_saved_size(hh_op op, const hh_desc *d, size_t *bytes) {
 hh_status hh_forward_save(hh_op op, const hh_desc *d, const void *U, int64_t ldu, const void *lam,
                           const void *X, int64_t ldx, void *Y, int64_t ldy, void *saved,
                           size_t saved_bytes, void *ws, size_t ws_bytes, hipStream_t stream) {
-    if (op != HH_OP_APPLY && op != HH_OP_APPLY_T && op != HH_OP_SYM)
+    if (!op_in(op, HH_OP_APPLY, HH_OP_SYM))
         return fail(HH_ERR_INVALID_ARG, "op must be HH_OP_APPLY, HH_OP_APPLY_T or HH_OP_SYM");
     HH_TRY(check_ptr("saved", saved));
     return forward(op, d, U, ldu, op == HH_OP_SYM ? lam : nullptr, X, ldx, nullptr, 0, Y, ldy, ws,
@@ -483,11 +503,11 @@ hh_status hh_forward_signed(hh_op op, const hh_desc *d, const void *U, int64_t l
                             const void *lam, const void *d_in, const void *d_out, const void *X,
                             int64_t ldx, const void *Xb, int64_t ldb, void *Y, int64_t ldy,
                             void *ws, size_t ws_bytes, hipStream_t stream) {
-    if (op != HH_OP_APPLY && op != HH_OP_APPLY_T && op != HH_OP_SYM && op != HH_OP_MAHAL)
+    if (!op_in(op, HH_OP_APPLY, HH_OP_MAHAL))
         return fail(HH_ERR_INVALID_ARG, "op must be a forward op");
-    if (!d) return fail(HH_ERR_INVALID_ARG, "desc must not be null");
+    Algo algo;
+    HH_TRY(check_desc(d, &algo));
     const size_t es = dtype_size(d->param_dtype);
-    if (es == 0) return fail(HH_ERR_INVALID_ARG, "unknown param_dtype");
     if (((uintptr_t)d_in % es) != 0 || ((uintptr_t)d_out % es) != 0)
         return fail(HH_ERR_INVALID_ARG, "d_in and d_out must be aligned to their element size");
     return forward(op, d, U, ldu, (op == HH_OP_SYM || op == HH_OP_MAHAL) ? lam : nullptr, X, ldx,
@@ -500,12 +520,11 @@ hh_status hh_backward_signed(hh_op op, const hh_desc *d, const void *U, int64_t 
                              int64_t ldx, const void *Xb, int64_t ldb, const void *dY, int64_t lddy,
                              void *dX, void *dXb, int64_t lddx, void *dU, int64_t lddu, void *dlam,
                              void *ws, size_t ws_bytes, hipStream_t stream) {
-    if (op != HH_OP_APPLY_BWD && op != HH_OP_APPLY_T_BWD && op != HH_OP_SYM_BWD &&
-        op != HH_OP_MAHAL_BWD)
+    if (!op_in(op, HH_OP_APPLY_BWD, HH_OP_MAHAL_BWD))
         return fail(HH_ERR_INVALID_ARG, "op must be a backward op");
-    if (!d) return fail(HH_ERR_INVALID_ARG, "desc must not be null");
+    Algo algo;
+    HH_TRY(check_desc(d, &algo));
     const size_t es = dtype_size(d->param_dtype);
-    if (es == 0) return fail(HH_ERR_INVALID_ARG, "unknown param_dtype");
     if (((uintptr_t)d_in % es) != 0 || ((uintptr_t)d_out % es) != 0)
         return fail(HH_ERR_INVALID_ARG, "d_in and d_out must be aligned to their element size");
     const bool mahal = op == HH_OP_MAHAL_BWD;
@@ -520,7 +539,7 @@ hh_status hh_backward_saved(hh_op op, const hh_desc *d, const void *U, int64_t l
                             size_t saved_bytes, const void *dY, int64_t lddy, void *dX,
                             int64_t lddx, void *dU, int64_t lddu, void *dlam, void *ws,
                             size_t ws_bytes, hipStream_t stream) {
-    if (op != HH_OP_APPLY_BWD && op != HH_OP_APPLY_T_BWD && op != HH_OP_SYM_BWD)
+    if (!op_in(op, HH_OP_APPLY_BWD, HH_OP_SYM_BWD))
         return fail(HH_ERR_INVALID_ARG,
                     "op must be HH_OP_APPLY_BWD, HH_OP_APPLY_T_BWD or HH_OP_SYM_BWD");
     HH_TRY(check_ptr("saved", saved));
