@@ -14,8 +14,12 @@
 //
 // A wave owns V vectors (64 lanes x NC 16-byte chunks each) and walks their
 // chains side by side: the V dot products of a step are independent, which
-// hides the latency of their cross-lane reductions.  Reflectors are read from
-// LDS when all h fit, otherwise straight from the workspace (L2).  dL/du for
+// hides the latency of their cross-lane reductions.  All h reflectors are
+// staged in LDS once per block (both sweeps walk them many times per vector);
+// shapes whose reflectors and per-vector state exceed the 64 KB LDS budget are
+// refused (HH_ERR_UNSUPPORTED; for FP32 h <= 29 at n = 512, h <= 13 at
+// n = 1024, h <= 1 at n = 4096, FP64 about half) and take the WY backward in
+// 16 bits.  dL/du for
 // HB reflectors at a time stays in registers across all the vectors a block
 // processes (shared by the V vectors of a wave); larger h takes several passes.  Each block writes its partial
 // sums; a second kernel adds the block partials in a fixed order in FP64

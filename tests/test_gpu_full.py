@@ -148,3 +148,46 @@ def test_full_sym_wy_fp16_fwd_bwd():
     assert rel_fro(host(dlam), rdlam) < TOL16
     del X, G, dX, rec
     release()
+
+
+def _row_rel(A, B, chunk=1 << 15):
+    """max over rows of ||a_j - b_j|| / ||b_j||, formed on the GPU in FP32
+    chunk by chunk (a checker over every vector of a full batch)."""
+    worst = 0.0
+    for s in range(0, A.shape[0], chunk):
+        a, b = A[s:s + chunk].float(), B[s:s + chunk].float()
+        r = torch.linalg.vector_norm(a - b, dim=1) / torch.linalg.vector_norm(b, dim=1)
+        worst = max(worst, float(r.max()))
+    return worst
+
+
+def _norm_dev(A, B, chunk=1 << 15):
+    """max over rows of | ||a_j|| - ||b_j|| | / ||b_j|| (GPU, FP32)."""
+    worst = 0.0
+    for s in range(0, A.shape[0], chunk):
+        na = torch.linalg.vector_norm(A[s:s + chunk].float(), dim=1)
+        nb = torch.linalg.vector_norm(B[s:s + chunk].float(), dim=1)
+        worst = max(worst, float(((na - nb).abs() / nb).max()))
+    return worst
+
+
+@pytest.mark.parametrize("n,h,N,dname", [(4096, 64, 1 << 18, "bf16"), (8192, 128, 1 << 16, "f16")])
+def test_full_wy_every_vector(n, h, N, dname):
+    """Invariants over every vector of the full batch (no oracle needed, so no
+    tile escapes the check): Q preserves each vector's norm, within the
+    output tolerance (| ||y|| - ||x|| | <= ||y^ - y||), and Q^T (Q x) = x
+    within twice it (two applications)."""
+    dt = {"bf16": torch.bfloat16, "f16": torch.float16}[dname]
+    U = torch.tensor(synth.reflectors(n, h, seed=0), dtype=torch.float32, device=dev())
+    X = synth.device_gaussian((N, n), seed=0, stream=synth.STREAM_X, device=dev(), dtype=dt)
+    Y = P.apply_raw(U, X, compute=dt)
+    assert _norm_dev(Y, X) < TOL16
+    Z = P.apply_raw(U, Y, trans=True, compute=dt)
+    assert _row_rel(Z, X) < 2 * TOL16
+    del Y, Z
+    # the symmetric form with lam = c everywhere is c X for every vector
+    lam = torch.full((n,), 3.0, dtype=torch.float32, device=dev())
+    S = P.sym_raw(U, lam, X, compute=dt)
+    assert _row_rel(S, 3.0 * X.float()) < TOL16
+    del X, S
+    release()
