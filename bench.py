@@ -54,6 +54,9 @@ WORKLOADS = {
     "sym_fb_n8192_h128": ("sym_fb", 8192, 128, 1 << 16, "f16",
                           "Q diag(lam) Q^T X forward + backward (dX, dU, dlam), n=8192, h=128, "
                           "N=2^16; compact-WY FP16"),
+    "qr_n512_h511": ("apply_qr", 512, 511, 1 << 20, "f32",
+                     "Q X with h = n - 1 reflectors of Householder QR structure (k - 1 leading "
+                     "zeros, the remark after Result 3), n=512, N=2^20; fused FP32"),
     "copy_n4096_bf16": ("copy", 4096, 0, 1 << 18, "bf16",
                         "device copy of the Q X batch (2 GiB in, 2 GiB out): HBM calibration"),
 }
@@ -79,6 +82,8 @@ def algorithmic(op, n, h, N, io_bytes, param_bytes=4):
     product; (4h+3)n per distance) for one call over N vectors."""
     if op in ("apply", "copy"):
         return 2 * n * io_bytes * N, 4 * n * h * N
+    if op == "apply_qr":   # reflector k has n - k + 1 nonzeros: 4(n - k + 1) operations
+        return 2 * n * io_bytes * N, 4 * sum(n - k + 1 for k in range(1, h + 1)) * N
     if op == "sym":
         return 2 * n * io_bytes * N, (8 * h + 1) * n * N
     if op == "sym_d":      # the two diagonal products: 2n more
@@ -159,7 +164,10 @@ def main():
     io_dt = tdt
     pdt = torch.float64 if comp == "f64" else torch.float32
 
-    U = torch.tensor(synth.reflectors(n, h, seed=0), dtype=pdt, device=dev)
+    if op == "apply_qr":
+        U = torch.tensor(synth.structured_reflectors(n, h, seed=0), dtype=pdt, device=dev)
+    else:
+        U = torch.tensor(synth.reflectors(n, h, seed=0), dtype=pdt, device=dev)
     lam_np = (synth.eig_loguniform(n, seed=0) if op == "sym_fb" else synth.eig_uniform(n, seed=0))
     lam = torch.tensor(lam_np, dtype=pdt, device=dev)
     X = synth.device_gaussian((N, n), seed=0, stream=synth.STREAM_X, device=dev, dtype=io_dt)
@@ -172,7 +180,8 @@ def main():
     Gd = None
     if op in ("apply_fb", "sym_fb"):
         Gd = synth.device_gaussian((N, n), seed=0, stream=synth.STREAM_G, device=dev, dtype=io_dt)
-    Y = torch.empty_like(X) if op in ("apply", "sym", "sym_d", "copy", "apply_fb", "sym_fb") else None
+    Y = torch.empty_like(X) if op in ("apply", "apply_qr", "sym", "sym_d", "copy", "apply_fb",
+                                      "sym_fb") else None
     dsig = None
     if op == "sym_d":
         dsig = torch.tensor(np.where(synth.host_rng(0, 11).random(n) < 0.5, -1.0, 1.0), dtype=pdt, device=dev)
@@ -183,6 +192,8 @@ def main():
             Y.copy_(X)
         elif op == "apply":
             P.apply_raw(U, X, compute=tdt, out=Y)
+        elif op == "apply_qr":
+            P.apply_raw(U, X, compute=tdt, out=Y, algo="fused_qr")
         elif op == "sym":
             P.sym_raw(U, lam, X, compute=tdt, out=Y)
         elif op == "sym_d":
@@ -221,14 +232,14 @@ def main():
     # kernels (normalisation, T), so the same call on a single vector is timed
     # the same way and subtracted (its main kernel is one tile, a few us).
     ms_setup = 0.0
-    if op in ("apply", "sym", "sym_d", "mahal"):
+    if op in ("apply", "apply_qr", "sym", "sym_d", "mahal"):
         X1 = X[:1]
         Y1 = Y[:1] if Y is not None else None
         Xb1 = Xb[:1] if Xb is not None else None
 
         def step1():
-            if op == "apply":
-                P.apply_raw(U, X1, compute=tdt, out=Y1)
+            if op in ("apply", "apply_qr"):
+                P.apply_raw(U, X1, compute=tdt, out=Y1, algo="fused_qr" if op == "apply_qr" else "auto")
             elif op == "sym":
                 P.sym_raw(U, lam, X1, compute=tdt, out=Y1)
             elif op == "sym_d":
@@ -324,6 +335,21 @@ def main():
         del Xf, Yf
         Y = None
 
+    # the same reflectors through the dense kernels, timed beside
+    if op == "apply_qr":
+        P.apply_raw(U, X, out=Y, algo="fused")
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        kf = max(1, min(args.steps, 5))
+        a.record(stream)
+        for _ in range(kf):
+            P.apply_raw(U, X, out=Y, algo="fused")
+        b.record(stream)
+        torch.cuda.synchronize()
+        msd = a.elapsed_time(b) / kf
+        out["dense_kernels"] = {"ms_per_call": msd, "vectors_per_s": N / (msd * 1e-3),
+                                "skip_speedup": msd / ms_wall}
+
     # accuracy on a sample of vectors, and the oracle's own speed on it
     if not args.no_cpu and op in ("apply_fb", "sym_fb"):
         import oracle
@@ -361,7 +387,7 @@ def main():
         out["cpu_baseline"] = {"value": S / tcpu, "unit": "vectors/s (forward + backward)",
                                "cores": oracle.num_threads(), "kind": "oracle",
                                "sample": f"first {S} of {N} vectors of the same batch, FP64"}
-    if not args.no_cpu and op in ("apply", "sym", "sym_d", "mahal", "mahal_fb"):
+    if not args.no_cpu and op in ("apply", "apply_qr", "sym", "sym_d", "mahal", "mahal_fb"):
         import oracle
         Uh = U.double().cpu().numpy()
         lh = lam.double().cpu().numpy()
@@ -369,7 +395,7 @@ def main():
         Xs = X[:S].double().cpu().numpy()
         t = time.perf_counter()
         dh = dsig.double().cpu().numpy() if dsig is not None else None
-        if op == "apply":
+        if op in ("apply", "apply_qr"):
             ref = oracle.apply(Uh, Xs)
         elif op == "sym":
             ref = oracle.sym(Uh, lh, Xs)
@@ -382,7 +408,7 @@ def main():
         S2 = int(min(N, max(S, S * args.cpu_seconds / max(t1, 1e-4))))
         Xs2 = X[:S2].double().cpu().numpy()
         t = time.perf_counter()
-        if op == "apply":
+        if op in ("apply", "apply_qr"):
             oracle.apply(Uh, Xs2)
         elif op == "sym":
             oracle.sym(Uh, lh, Xs2)
@@ -398,8 +424,8 @@ def main():
         out["cpu_baseline"] = {"value": S2 / tcpu, "unit": "vectors/s",
                                "cores": oracle.num_threads(), "kind": "oracle",
                                "sample": f"first {S2} of {N} vectors of the same batch, FP64"}
-        if op in ("apply", "sym", "sym_d"):
-            Yg = (P.apply_raw(U, X[:S], compute=tdt) if op == "apply" else
+        if op in ("apply", "apply_qr", "sym", "sym_d"):
+            Yg = (P.apply_raw(U, X[:S], compute=tdt) if op in ("apply", "apply_qr") else
                   P.sym_raw(U, lam, X[:S], compute=tdt) if op == "sym" else
                   P.signed_raw("sym", U, X[:S], d_in=dsig, d_out=dsig, lam=lam, compute=tdt)
                   ).double().cpu().numpy()

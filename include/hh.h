@@ -93,7 +93,14 @@ typedef enum {
 
 typedef enum { HH_F64 = 0, HH_F32 = 1, HH_BF16 = 2, HH_F16 = 3 } hh_dtype;
 
-typedef enum { HH_ALGO_AUTO = 0, HH_ALGO_FUSED = 1, HH_ALGO_WY = 2 } hh_algo;
+/* HH_ALGO_FUSED_QR: the FUSED algorithm with forward kernels that leave out
+ * each reflector's leading zeros, in whole 16-byte chunks of every lane's
+ * slice (the first nonzero entry is found in the setup).  Reflectors of a
+ * Householder QR have k - 1 leading zeros (the remark after Result 3: an
+ * application costs 4(n - k + 1) operations instead of 4n); at h = n - 1 that
+ * halves the work.  Results are those of FUSED (skipped terms are exact
+ * zeros); any reflectors are accepted.  Backward calls run as FUSED. */
+typedef enum { HH_ALGO_AUTO = 0, HH_ALGO_FUSED = 1, HH_ALGO_WY = 2, HH_ALGO_FUSED_QR = 3 } hh_algo;
 
 typedef enum {
     HH_OP_APPLY = 0,

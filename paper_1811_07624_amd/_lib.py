@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_PKG, "libhh.so")
 
 HH_OK, HH_ERR_INVALID_ARG, HH_ERR_UNSUPPORTED, HH_ERR_WORKSPACE, HH_ERR_HIP = range(5)
 HH_F64, HH_F32, HH_BF16, HH_F16 = range(4)
-HH_ALGO_AUTO, HH_ALGO_FUSED, HH_ALGO_WY = range(3)
+HH_ALGO_AUTO, HH_ALGO_FUSED, HH_ALGO_WY, HH_ALGO_FUSED_QR = range(4)
 (HH_OP_APPLY, HH_OP_APPLY_T, HH_OP_SYM, HH_OP_MAHAL, HH_OP_APPLY_BWD, HH_OP_APPLY_T_BWD,
  HH_OP_SYM_BWD, HH_OP_MAHAL_BWD) = range(8)
 
@@ -33,7 +33,8 @@ NOALLOC_SCRATCH_BYTES = 16 << 20
 
 _TORCH_TO_HH = {torch.float64: HH_F64, torch.float32: HH_F32, torch.bfloat16: HH_BF16,
                 torch.float16: HH_F16}
-_ALGOS = {"auto": HH_ALGO_AUTO, "fused": HH_ALGO_FUSED, "wy": HH_ALGO_WY}
+_ALGOS = {"auto": HH_ALGO_AUTO, "fused": HH_ALGO_FUSED, "wy": HH_ALGO_WY,
+          "fused_qr": HH_ALGO_FUSED_QR}
 
 
 class HHDesc(ctypes.Structure):

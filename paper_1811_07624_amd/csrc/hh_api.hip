@@ -88,9 +88,9 @@ static hh_status check_desc(const hh_desc *d, Algo *algo) {
         !valid_dtype(raw_code(d->compute_dtype)))
         return fail(HH_ERR_INVALID_ARG, "unknown dtype code");
     const int ac = raw_code(d->algo);
-    if (ac != HH_ALGO_AUTO && ac != HH_ALGO_FUSED && ac != HH_ALGO_WY)
+    if (ac != HH_ALGO_AUTO && ac != HH_ALGO_FUSED && ac != HH_ALGO_WY && ac != HH_ALGO_FUSED_QR)
         return fail(HH_ERR_INVALID_ARG, "unknown algo code");
-    hh_algo a = d->algo;
+    hh_algo a = d->algo == HH_ALGO_FUSED_QR ? HH_ALGO_FUSED : d->algo;
     if (a == HH_ALGO_AUTO)
         a = (d->compute_dtype == HH_F64 || d->compute_dtype == HH_F32) ? HH_ALGO_FUSED : HH_ALGO_WY;
     if (a == HH_ALGO_FUSED) {
@@ -131,7 +131,7 @@ static hh_status check_ptr(const char *name, const void *p) {
 // ---------------------------------------------------------------------------
 // Workspace layout of the fused path.
 struct FusedWs {
-    size_t ut, tau, lam, uh64, nrm64, bwd, total;
+    size_t ut, tau, lead, lam, uh64, nrm64, bwd, total;
 };
 
 static bool is_bwd(hh_op op) { return op >= HH_OP_APPLY_BWD; }
@@ -146,6 +146,7 @@ static FusedWs fused_ws(hh_op op, const FusedPlan &p) {
     size_t off = 0;
     w.ut = off;   off += align256(h * npad * es);
     w.tau = off;  off += align256(std::max<size_t>(h, 1) * es);
+    w.lead = off; off += is_bwd(op) ? 0 : align256(std::max<size_t>(h, 1) * 4);
     w.lam = off;  off += uses_lam(op) ? align256(npad * es) : 0;
     w.uh64 = off; off += is_bwd(op) ? align256(h * (size_t)p.n * 8) : 0;
     w.nrm64 = off; off += is_bwd(op) ? align256(std::max<size_t>(h, 1) * 8) : 0;
@@ -217,7 +218,8 @@ static hh_status forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
     char *base = static_cast<char *>(ws);
     hipError_t e = launch_setup_fused(p.t, U, ldu, uses_lam(op) ? lam : nullptr, n, h, p.s.npad,
                                       base + w.ut, base + w.tau,
-                                      uses_lam(op) ? base + w.lam : nullptr, nullptr, nullptr, st);
+                                      uses_lam(op) ? base + w.lam : nullptr, nullptr, nullptr,
+                                      reinterpret_cast<int *>(base + w.lead), st);
     if (e != hipSuccess) return hip_fail(e, "setup launch");
 
     const size_t es = dtype_size(p.t);
@@ -231,6 +233,7 @@ static hh_status forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
     a.ldy = ldy;
     a.ut = base + w.ut;
     a.tau = base + w.tau;
+    a.lead = reinterpret_cast<const int *>(base + w.lead);
     a.lam = base + w.lam;
     a.din = din;
     a.dout = dout;
@@ -243,6 +246,7 @@ static hh_status forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
     if (op == HH_OP_MAHAL) vec = vec && aligned16(Xb) && (ldb % wvec == 0);
     else vec = vec && aligned16(Y) && (ldy % wvec == 0);
     a.vec_ok = vec ? 1 : 0;
+    a.skip_zeros = d->algo == HH_ALGO_FUSED_QR ? 1 : 0;
     FusedOp fop = op == HH_OP_APPLY ? F_APPLY : op == HH_OP_APPLY_T ? F_APPLY_T
                 : op == HH_OP_SYM ? F_SYM : F_MAHAL;
     e = launch_fused_fwd(p, fop, a, st);
@@ -300,7 +304,7 @@ static hh_status backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu
                                       base + w.ut, base + w.tau,
                                       uses_lam(op) ? base + w.lam : nullptr,
                                       reinterpret_cast<double *>(base + w.uh64),
-                                      reinterpret_cast<double *>(base + w.nrm64), st);
+                                      reinterpret_cast<double *>(base + w.nrm64), nullptr, st);
     if (e != hipSuccess) return hip_fail(e, "setup launch");
     const size_t es = dtype_size(p.t);
     const int wvec = 16 / (int)es;

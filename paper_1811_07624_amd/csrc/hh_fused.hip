@@ -14,6 +14,10 @@
 // spectrum) are staged in LDS, all at once when they fit, otherwise in chunks
 // of hc reflectors that every wave of the block walks through in lockstep;
 // each chunk of a reflector read from LDS serves the VPL vectors of the group.
+// A reflector whose first nonzero entry lies past whole chunks (reflectors of
+// a Householder QR have k - 1 leading zeros, the remark after Result 3) skips
+// those chunks in its dot product and update: 4(n - k + 1) operations instead
+// of 4n, with the same result (the skipped terms are exact zeros).
 #include <algorithm>
 #include <type_traits>
 
@@ -25,7 +29,7 @@ namespace {
 constexpr size_t kLdsBudget = 64 * 1024;       // several blocks per compute unit
 constexpr size_t kLdsBudgetWide = 144 * 1024;  // one 8-wave block per compute unit
 
-template <typename T, int LPV, int NC, int OP, int VPL, int WPB>
+template <typename T, int LPV, int NC, int OP, int VPL, int WPB, bool SKIP>
 __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
     using VT = typename V16<T>::type;
     constexpr int W = V16<T>::W;
@@ -41,6 +45,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
     T *sDin = sLam + npad;                         // diagonal on the input (if given)
     T *sDout = sDin + (a.din ? npad : 0);          // diagonal on the output (if given)
     T *sTau = sDout + (a.dout ? npad : 0);         // tau of the reflectors of the current chunk
+    int *sLead = reinterpret_cast<int *>(sTau + hc);  // leading zero chunks (SKIP)
     const T *gU = static_cast<const T *>(a.ut);
     const T *gTau = static_cast<const T *>(a.tau);
 
@@ -64,7 +69,8 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
     __syncthreads();
 
     const int nchunks = h > 0 ? (h + hc - 1) / hc : 0;
-    int loaded = -1;  // block-uniform
+    int loaded = -1;      // block-uniform
+    int chunk_skip = 0;   // block-uniform: leading zero chunks shared by every reflector of the loaded chunk
     auto load_chunk = [&](int q) {
         if (q == loaded) return;
         __syncthreads();
@@ -72,20 +78,49 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
         const int cnt = min(hc, h - k0);
         const VT *src = reinterpret_cast<const VT *>(gU + (size_t)k0 * npad);
         VT *dst = reinterpret_cast<VT *>(sU);
-        const int total = cnt * (npad / W);
-        for (int i = tid; i < total; i += kThreads) dst[i] = src[i];
-        for (int i = tid; i < cnt; i += kThreads) sTau[i] = gTau[k0 + i];
-        __syncthreads();
+        if constexpr (SKIP) {
+            // the fewest leading zero chunks over the chunk's reflectors
+            // (QR reflectors: k - 1 leading zeros, so this changes slowly);
+            // those chunks are neither staged nor read
+            if (tid == 0) sLead[0] = NC;
+            __syncthreads();
+            int mn = NC;
+            for (int i = tid; i < cnt; i += kThreads) {
+                sTau[i] = gTau[k0 + i];
+                mn = min(mn, a.lead[k0 + i] / STR);
+            }
+            if (mn < NC) atomicMin(&sLead[0], mn);
+            __syncthreads();
+            // in steps of G chunks, at most eight loop variants (run_chunk)
+            constexpr int NV = NC < 8 ? NC : 8;
+            constexpr int G = NC / NV;
+            chunk_skip = min(sLead[0] / G, NV - 1) * G;
+            const int off = chunk_skip * (STR / W);  // skipped 16-byte pieces per reflector
+            const int per = npad / W - off;
+            const int total = cnt * per;
+            for (int i = tid; i < total; i += kThreads) {
+                const int r = i / per, e = off + i % per;
+                dst[r * (npad / W) + e] = src[r * (npad / W) + e];
+            }
+            __syncthreads();
+        } else {
+            const int total = cnt * (npad / W);
+            for (int i = tid; i < total; i += kThreads) dst[i] = src[i];
+            for (int i = tid; i < cnt; i += kThreads) sTau[i] = gTau[k0 + i];
+            __syncthreads();
+        }
         loaded = q;
     };
     if (nchunks == 1) load_chunk(0);
 
-    // One reflection of the lane's slices of its VPL vectors by reflector k.
-    auto reflect = [&](int k, T(&x)[VPL][E]) {
+    // One reflection of the lane's slices of its VPL vectors by reflector k,
+    // over chunks S .. NC-1 (S = 0: the whole vector).
+    auto reflect_from = [&](auto S0, int k, T(&x)[VPL][E]) {
+        constexpr int S = decltype(S0)::value;
         const T *u = sU + (size_t)(k - loaded * hc) * npad + c * W;
         VT uv[NC];
 #pragma unroll
-        for (int i = 0; i < NC; ++i) uv[i] = *reinterpret_cast<const VT *>(u + i * STR);
+        for (int i = S; i < NC; ++i) uv[i] = *reinterpret_cast<const VT *>(u + i * STR);
         const T tk = sTau[k - loaded * hc];
 #pragma unroll
         for (int v = 0; v < VPL; ++v) {
@@ -93,7 +128,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
 #pragma unroll
             for (int q = 0; q < W; ++q) part[q] = (T)0;
 #pragma unroll
-            for (int i = 0; i < NC; ++i)
+            for (int i = S; i < NC; ++i)
 #pragma unroll
                 for (int q = 0; q < W; ++q) part[q] = fmat(uv[i][q], x[v][i * W + q], part[q]);
             T p = part[0];
@@ -102,9 +137,29 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
             p = group_sum<LPV>(p);
             const T coef = -p * tk;
 #pragma unroll
-            for (int i = 0; i < NC; ++i)
+            for (int i = S; i < NC; ++i)
 #pragma unroll
                 for (int q = 0; q < W; ++q) x[v][i * W + q] = fmat(coef, uv[i][q], x[v][i * W + q]);
+        }
+    };
+    // The reflectors of a chunk that all start past chunk S of every lane's
+    // slice (S = chunk_skip, a multiple of G): one scalar dispatch per LDS
+    // chunk to the loop that leaves out chunks 0 .. S-1 (at most eight
+    // variants).
+    auto run_chunk = [&](int kb, int ke, int step, T(&x)[VPL][E]) {
+        auto loop = [&](auto S0) {
+#pragma unroll 1
+            for (int k = kb; k != ke; k += step) reflect_from(S0, k, x);
+        };
+        if constexpr (SKIP) {
+            constexpr int NV = NC < 8 ? NC : 8;
+            constexpr int G = NC / NV;
+            const int sv = __builtin_amdgcn_readfirstlane(chunk_skip) / G;
+            static_for<NV>([&](auto cc) {
+                if (sv == decltype(cc)::value) loop(std::integral_constant<int, decltype(cc)::value * G>{});
+            });
+        } else {
+            loop(std::integral_constant<int, 0>{});
         }
     };
     // x <- diag(d) x on the lane's slices (d staged in LDS like the spectrum)
@@ -123,8 +178,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
         for (int q = 0; q < nchunks; ++q) {
             load_chunk(q);
             const int kend = min(h, (q + 1) * hc);
-#pragma unroll 1
-            for (int k = q * hc; k < kend; ++k) reflect(k, x);
+            run_chunk(q * hc, kend, 1, x);
         }
     };
     auto run_down = [&](T(&x)[VPL][E]) {  // k = h-1 .. 0  (Q: H_h first)
@@ -132,8 +186,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
         for (int q = nchunks - 1; q >= 0; --q) {
             load_chunk(q);
             const int kend = min(h, (q + 1) * hc);
-#pragma unroll 1
-            for (int k = kend - 1; k >= q * hc; --k) reflect(k, x);
+            run_chunk(kend - 1, q * hc - 1, -1, x);
         }
     };
     auto load_vec = [&](T(&x)[E], const T *base, int64_t ld, int64_t j, bool valid) {
@@ -254,25 +307,34 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
     }
 }
 
-template <typename T, int LPV, int NC, int VPL = 1, int WPB = 4>
-hipError_t launch_op(FusedOp op, const FusedPlan &p, const FusedFwdArgs &a, dim3 grid,
-                     hipStream_t st) {
+template <typename T, int LPV, int NC, int VPL, int WPB, bool SKIP>
+hipError_t launch_op_s(FusedOp op, const FusedPlan &p, const FusedFwdArgs &a, dim3 grid,
+                       hipStream_t st) {
     const dim3 block(WPB * kWave);
     switch (op) {
     case F_APPLY:
-        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_APPLY, VPL, WPB>), grid, block, p.lds_bytes, st, a);
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_APPLY, VPL, WPB, SKIP>), grid, block, p.lds_bytes, st, a);
         break;
     case F_APPLY_T:
-        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_APPLY_T, VPL, WPB>), grid, block, p.lds_bytes, st, a);
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_APPLY_T, VPL, WPB, SKIP>), grid, block, p.lds_bytes, st, a);
         break;
     case F_SYM:
-        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_SYM, VPL, WPB>), grid, block, p.lds_bytes, st, a);
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_SYM, VPL, WPB, SKIP>), grid, block, p.lds_bytes, st, a);
         break;
     case F_MAHAL:
-        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_MAHAL, VPL, WPB>), grid, block, p.lds_bytes, st, a);
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_MAHAL, VPL, WPB, SKIP>), grid, block, p.lds_bytes, st, a);
         break;
     }
     return hipGetLastError();
+}
+
+// skip: the kernels that leave out each reflector's leading zero chunks
+// (HH_ALGO_FUSED_QR); the others treat every reflector as dense.
+template <typename T, int LPV, int NC, int VPL = 1, int WPB = 4>
+hipError_t launch_op(FusedOp op, const FusedPlan &p, const FusedFwdArgs &a, dim3 grid,
+                     hipStream_t st) {
+    return a.skip_zeros ? launch_op_s<T, LPV, NC, VPL, WPB, true>(op, p, a, grid, st)
+                        : launch_op_s<T, LPV, NC, VPL, WPB, false>(op, p, a, grid, st);
 }
 
 template <typename T>
@@ -356,7 +418,8 @@ bool fused_plan(hh_dtype t, int64_t n, int64_t h, int64_t N, FusedPlan *p, int n
     if (fixed + vec_bytes > budget) return false;
     const int64_t fit = (int64_t)((budget - fixed) / vec_bytes);
     p->hc = (int)std::max<int64_t>(1, std::min<int64_t>(h, fit));
-    p->lds_bytes = fixed + (size_t)p->hc * (vec_bytes + es);  // reflectors and their tau
+    // reflectors, their tau and their leading zero chunk counts
+    p->lds_bytes = fixed + (size_t)p->hc * (vec_bytes + es + sizeof(int));
     return true;
 }
 

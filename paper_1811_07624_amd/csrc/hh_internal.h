@@ -150,10 +150,13 @@ struct FusedPlan {
     size_t lds_bytes;
 };
 
-// Setup: uh (FP64), compute-type padded reflectors, tau, padded lam.
+// Setup: uh (FP64), compute-type padded reflectors, tau, padded lam, and
+// (nullable) lead[k] = index of the first nonzero entry of the compute-type
+// reflector k (npad for a zero reflector).
 hipError_t launch_setup_fused(hh_dtype t, const void *U, int64_t ldu, const void *lam,
                               int64_t n, int64_t h, int npad, void *ut, void *tau,
-                              void *lamp, double *uh64, double *nrm64, hipStream_t st);
+                              void *lamp, double *uh64, double *nrm64, int *lead,
+                              hipStream_t st);
 
 enum FusedOp { F_APPLY = 0, F_APPLY_T = 1, F_SYM = 2, F_MAHAL = 3 };
 
@@ -166,12 +169,14 @@ struct FusedFwdArgs {
     int64_t ldy;
     const void *ut;
     const void *tau;
+    const int *lead;   // first nonzero entry of each compute-type reflector
     const void *lam;
     const void *din;   // n diagonal entries applied to the input, or null
     const void *dout;  // n diagonal entries applied to the output, or null
     int n, h, npad, hc;
     int64_t N;
     int vec_ok;  // 16-byte accesses are legal for every data operand
+    int skip_zeros;  // run the kernels that skip each reflector's leading zero chunks
 };
 
 hipError_t launch_fused_fwd(const FusedPlan &p, FusedOp op, const FusedFwdArgs &a,

@@ -11,7 +11,9 @@ returns; no arithmetic on the data happens in Python.
 sequential-reflector kernels (data in that dtype); bfloat16/float16 run the
 compact-WY matrix-core kernels (data in that dtype or in float32, which the
 library rounds to the compute type and widens back; parameters in float32).
-``algo`` may force "fused" or "wy"; the default "auto" follows ``compute``.
+``algo`` may force "fused" or "wy"; the default "auto" follows ``compute``;
+"fused_qr" runs the fused forward kernels that skip each reflector's leading
+zeros (reflectors of a Householder QR, the remark after Result 3).
 
 On the WY path a forward whose reflectors (or spectrum) need a gradient keeps
 a record of its per-vector WY coefficients (h scalars per vector, not h copies

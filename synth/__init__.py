@@ -36,6 +36,18 @@ def reflectors(n: int, h: int, seed: int = 0, normalize: bool = True) -> np.ndar
     return U
 
 
+def structured_reflectors(n: int, h: int, seed: int = 0) -> np.ndarray:
+    """(h, n) float64 with the sparsity of Householder QR reflectors (the
+    remark after Result 3): row k (0-based) has k leading zeros, the rest
+    N(0, 1), scaled to unit length."""
+    U = host_rng(seed, STREAM_U).standard_normal((h, n))
+    for k in range(min(h, n)):
+        U[k, :k] = 0.0
+    if h > 0:
+        U = U / np.linalg.norm(U, axis=1, keepdims=True)
+    return U
+
+
 def eig_uniform(n: int, lo: float = 0.1, hi: float = 10.0, seed: int = 0) -> np.ndarray:
     return host_rng(seed, STREAM_LAM).uniform(lo, hi, size=n)
 
