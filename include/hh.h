@@ -280,6 +280,44 @@ HH_API hh_status hh_backward_signed(hh_op op, const hh_desc *d, const void *U, i
                              int64_t lddx, void *dU, int64_t lddu, void *dlam, void *ws,
                              size_t ws_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Orthonormal factorisation front-end (Sec. II-B to II-D), FP64 on the GPU:
+ * reflectors R (n x h, column k = unit vector u_k or zero, ld ldr >= n) that
+ * approximate a given orthonormal U (n x n, ld ldu >= n) as
+ * Q = H_1 ... H_h (the order every call above uses), ready for hh_apply etc.
+ *   HH_FACTOR_CONSTRAINED   Result 1: mutually orthogonal reflectors, the
+ *                           eigenvectors of the negative eigenvalues of
+ *                           Z = U + U^T, smallest first; error
+ *                           2n - 2 tr U + 2 sum of those eigenvalues
+ *                           (eq. bestortho at h = n_-).
+ *   HH_FACTOR_UNCONSTRAINED Result 2: Case 1 / Case 2 reflectors along the
+ *                           spectrum of Z (eq. theu2); error 2 n_+ - sum of
+ *                           the nonnegative z at h = n_- (eq. result2).
+ *   HH_FACTOR_QR            Result 3: the first h <= n - 1 reflectors of the
+ *                           Householder QR of U and the +-1 diagonal d with
+ *                           U ~ Q diag(d) (hh_forward_signed with d_in = d);
+ *                           reflector k has k - 1 leading zeros
+ *                           (HH_ALGO_FUSED_QR skips them).
+ * Reflectors beyond the useful ones (no negative eigenvalue left) are zero
+ * columns, i.e. identity factors.  d (n values, nullable): the QR diagonal,
+ * all ones for the other methods.  z (n values, nullable): the eigenvalues of
+ * U + U^T in ascending order (eigen methods; untouched for QR).  Sizes:
+ * n <= 1024 for the eigen methods (cyclic Jacobi, at most 16 sweeps), n <=
+ * 4096 for QR.  Workspace of hh_factor_workspace_size bytes; stream-ordered
+ * and asynchronous like the transform calls. */
+typedef enum {
+    HH_FACTOR_CONSTRAINED = 0,
+    HH_FACTOR_UNCONSTRAINED = 1,
+    HH_FACTOR_QR = 2
+} hh_factor_method;
+
+HH_API hh_status hh_factor_workspace_size(hh_factor_method method, int64_t n, int64_t h,
+                                          size_t *bytes);
+HH_API hh_status hh_factor_orthonormal(hh_factor_method method, int64_t n, int64_t h,
+                                       const double *U, int64_t ldu, double *R, int64_t ldr,
+                                       double *d, double *z, void *ws, size_t ws_bytes,
+                                       hipStream_t stream);
+
 /* Size of the static device scratch of hh_forward_noalloc (16 MiB, held by
  * each GPU the library runs on until the process ends). */
 #define HH_NOALLOC_SCRATCH_BYTES (16u << 20)

@@ -462,3 +462,36 @@ def sym_apply(U, lam, X, *, compute=None, algo="auto"):
 def mahalanobis(U, lam, Xa, Xb, *, compute=None, algo="auto"):
     """d_j = sum_i lam_i ((Q^T (xa_j - xb_j))_i)^2."""
     return _Mahal.apply(U, lam, Xa, Xb, compute, algo)
+
+
+# --------------------------------------------------------------------------
+# orthonormal factorisation front-end
+# --------------------------------------------------------------------------
+_FACTOR = {"constrained": L.HH_FACTOR_CONSTRAINED, "unconstrained": L.HH_FACTOR_UNCONSTRAINED,
+           "qr": L.HH_FACTOR_QR}
+
+
+def factor_orthonormal(U, h, method="unconstrained"):
+    """Reflectors approximating the orthonormal (n, n) matrix U (math
+    orientation, device tensor): "constrained" (Result 1), "unconstrained"
+    (Result 2) or "qr" (Result 3).  Returns (R, d, z): R (h, n) float64 in the
+    library's reflector layout (row k = u_k, Q = H_1 ... H_h approximates U,
+    or U ~ Q diag(d) for "qr"), d (n,) the sign diagonal (ones for the eigen
+    methods), z (n,) the eigenvalues of U + U^T ascending (eigen methods;
+    None for "qr")."""
+    _check_dev(U)
+    if U.dim() != 2 or U.shape[0] != U.shape[1]:
+        raise ValueError("U must be square")
+    n = U.shape[0]
+    Ut = U.to(torch.float64).t().contiguous()  # column-major: (column j) = row j of Ut
+    m = _FACTOR[method]
+    nb = ctypes.c_size_t(0)
+    L.check("hh_factor_workspace_size", L.lib().hh_factor_workspace_size(m, n, h, ctypes.byref(nb)))
+    ws = torch.empty((max(nb.value, 1),), dtype=torch.uint8, device=U.device)
+    R = torch.empty((h, n), dtype=torch.float64, device=U.device)
+    d = torch.empty((n,), dtype=torch.float64, device=U.device)
+    z = None if method == "qr" else torch.empty((n,), dtype=torch.float64, device=U.device)
+    L.check("hh_factor_orthonormal", L.lib().hh_factor_orthonormal(
+        m, n, h, L.ptr(Ut), n, L.ptr(R) if h else None, n, L.ptr(d), L.ptr(z), L.ptr(ws),
+        ws.numel(), L.stream_of(Ut)))
+    return R, d, z

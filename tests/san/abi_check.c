@@ -108,6 +108,13 @@ int main(void) {
            HH_ERR_WORKSPACE);
     EXPECT(hh_forward_noalloc(HH_OP_SYM_BWD, &d, U, 4096, NULL, X, 4096, NULL, 0, Y, 4096, NULL),
            HH_ERR_INVALID_ARG);
+    size_t fb = 0;
+    EXPECT(hh_factor_workspace_size(HH_FACTOR_QR, 4096, 4095, &fb), HH_OK);
+    EXPECT(hh_factor_workspace_size(HH_FACTOR_QR, 4096, 4096, &fb), HH_ERR_INVALID_ARG);
+    EXPECT(hh_factor_workspace_size((hh_factor_method)9, 64, 4, &fb), HH_ERR_INVALID_ARG);
+    EXPECT(hh_factor_workspace_size(HH_FACTOR_CONSTRAINED, (int64_t)1 << 40, 4, &fb), HH_ERR_UNSUPPORTED);
+    EXPECT(hh_factor_orthonormal(HH_FACTOR_UNCONSTRAINED, 16, 4, (const double *)U, 16, (double *)Y,
+                                 16, NULL, NULL, ws, 16, NULL), HH_ERR_WORKSPACE);
     EXPECT(hh_workspace_size((hh_op)42, &d, (size_t *)ws), HH_ERR_INVALID_ARG);
     EXPECT(hh_workspace_size(HH_OP_APPLY, &d, NULL), HH_ERR_INVALID_ARG);
     printf("host sanitizer check: %zu size queries, %d failure(s)\n", sweeps, failures);

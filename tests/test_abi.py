@@ -259,3 +259,29 @@ def test_noalloc_validation():
     big = L.HHDesc(4096, 64, 4096, L.HH_F32, L.HH_F32, L.HH_BF16, L.HH_ALGO_AUTO)  # 64 MiB copies
     assert call(L.HH_OP_APPLY, big) == L.HH_ERR_WORKSPACE
     assert b"static scratch" in lib.hh_last_error()
+
+
+def test_factor_validation():
+    """The front-end refuses bad arguments on the host before any device call."""
+    v = ctypes.c_void_p
+    lib = P.lib()
+    nb = ctypes.c_size_t(0)
+    assert lib.hh_factor_workspace_size(L.HH_FACTOR_QR, 64, 63, ctypes.byref(nb)) == L.HH_OK
+    assert nb.value >= 64 * 64 * 8
+    assert lib.hh_factor_workspace_size(L.HH_FACTOR_QR, 64, 64, ctypes.byref(nb)) == L.HH_ERR_INVALID_ARG
+    assert lib.hh_factor_workspace_size(7, 64, 4, ctypes.byref(nb)) == L.HH_ERR_INVALID_ARG
+    assert lib.hh_factor_workspace_size(L.HH_FACTOR_CONSTRAINED, 2048, 4, ctypes.byref(nb)) == \
+        L.HH_ERR_UNSUPPORTED
+    assert lib.hh_factor_workspace_size(L.HH_FACTOR_CONSTRAINED, 0, 4, ctypes.byref(nb)) == \
+        L.HH_ERR_INVALID_ARG
+
+    def call(n=16, h=4, U=1024, ldu=16, R=2048, ldr=16, ws=4096, wsb=1 << 20):
+        return lib.hh_factor_orthonormal(L.HH_FACTOR_UNCONSTRAINED, n, h, v(U) if U else None, ldu,
+                                         v(R) if R else None, ldr, None, None,
+                                         v(ws) if ws else None, wsb, None)
+    assert call(U=0) == L.HH_ERR_INVALID_ARG
+    assert call(ldu=15) == L.HH_ERR_INVALID_ARG
+    assert call(R=0) == L.HH_ERR_INVALID_ARG
+    assert call(ldr=3) == L.HH_ERR_INVALID_ARG
+    assert call(ws=0) == L.HH_ERR_INVALID_ARG
+    assert call(wsb=16) == L.HH_ERR_WORKSPACE
