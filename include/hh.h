@@ -318,6 +318,25 @@ HH_API hh_status hh_factor_orthonormal(hh_factor_method method, int64_t n, int64
                                        double *d, double *z, void *ws, size_t ws_bytes,
                                        hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Symmetric Householder Factorisation (Sec. III-B, Algorithm 1), FP64 on the
+ * GPU: for a symmetric S (n x n, ld lds >= n) finds reflectors R (n x h,
+ * column k = u_k, ld ldr >= n), a spectrum sbar (n) and a +-1 diagonal d (n)
+ * with Sbar = D U_1 ... U_h diag(sbar) U_h ... U_1 D (eq. thesbar) close to S:
+ * the initial reflectors of eq. combine, then K sweeps of the sphere descent
+ * of eq. iterate over all reflectors, each followed by the update of D
+ * (eq. optimaldiagonal) and, with spectrum_update != 0 (SHF-SU), of sbar
+ * (eq. updateofsbar); stops early when a sweep gains less than 1e-8 of the
+ * error.  err (K + 1 values, nullable) receives ||S - Sbar||_F^2 after the
+ * initialisation and after each sweep (repeated once stopped).  Sbar x is
+ * then hh_forward_signed(HH_OP_SYM, lam = sbar, d_in = d_out = d) with these
+ * reflectors.  n <= 512; one workgroup runs the whole algorithm (a set-up
+ * step).  Workspace of hh_shf_workspace_size bytes; asynchronous. */
+HH_API hh_status hh_shf_workspace_size(int64_t n, int64_t h, int64_t K, size_t *bytes);
+HH_API hh_status hh_shf(int64_t n, int64_t h, int64_t K, int spectrum_update, const double *S,
+                        int64_t lds, double *R, int64_t ldr, double *sbar, double *d, double *err,
+                        void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Size of the static device scratch of hh_forward_noalloc (16 MiB, held by
  * each GPU the library runs on until the process ends). */
 #define HH_NOALLOC_SCRATCH_BYTES (16u << 20)

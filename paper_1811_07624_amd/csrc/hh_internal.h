@@ -137,7 +137,7 @@ hh_status set_error(hh_status s, const char *fmt, ...) __attribute__((format(pri
 int device_cu_count();
 
 // Workspace layout helpers.
-inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+__host__ __device__ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // ---------------------------------------------------------------------------
 // Launchers (host side, enqueue only).  Each returns hipSuccess or the launch

@@ -495,3 +495,28 @@ def factor_orthonormal(U, h, method="unconstrained"):
         m, n, h, L.ptr(Ut), n, L.ptr(R) if h else None, n, L.ptr(d), L.ptr(z), L.ptr(ws),
         ws.numel(), L.stream_of(Ut)))
     return R, d, z
+
+
+def shf(S, h, K=30, spectrum_update=True):
+    """Symmetric Householder Factorisation of the symmetric (n, n) device
+    tensor S (Algorithm 1; SHF-SU when spectrum_update): returns (R, sbar, d,
+    err) with R (h, n) float64 reflectors (row k = u_k), so that
+    Sbar = D Q diag(sbar) Q^T D with Q = H_1 ... H_h (apply it with
+    signed("sym", R, X, d_in=d, d_out=d, lam=sbar)), and err (K + 1,) the
+    squared Frobenius errors after the initialisation and each sweep."""
+    _check_dev(S)
+    if S.dim() != 2 or S.shape[0] != S.shape[1]:
+        raise ValueError("S must be square")
+    n = S.shape[0]
+    St = S.to(torch.float64).contiguous()  # symmetric: row- and column-major agree
+    nb = ctypes.c_size_t(0)
+    L.check("hh_shf_workspace_size", L.lib().hh_shf_workspace_size(n, h, K, ctypes.byref(nb)))
+    ws = torch.empty((nb.value,), dtype=torch.uint8, device=S.device)
+    R = torch.empty((h, n), dtype=torch.float64, device=S.device)
+    sbar = torch.empty((n,), dtype=torch.float64, device=S.device)
+    d = torch.empty((n,), dtype=torch.float64, device=S.device)
+    err = torch.empty((K + 1,), dtype=torch.float64, device=S.device)
+    L.check("hh_shf", L.lib().hh_shf(n, h, K, 1 if spectrum_update else 0, L.ptr(St), n,
+                                     L.ptr(R) if h else None, n, L.ptr(sbar), L.ptr(d),
+                                     L.ptr(err), L.ptr(ws), ws.numel(), L.stream_of(St)))
+    return R, sbar, d, err

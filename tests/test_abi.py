@@ -285,3 +285,21 @@ def test_factor_validation():
     assert call(ldr=3) == L.HH_ERR_INVALID_ARG
     assert call(ws=0) == L.HH_ERR_INVALID_ARG
     assert call(wsb=16) == L.HH_ERR_WORKSPACE
+
+
+def test_shf_validation():
+    v = ctypes.c_void_p
+    lib = P.lib()
+    nb = ctypes.c_size_t(0)
+    assert lib.hh_shf_workspace_size(128, 16, 30, ctypes.byref(nb)) == L.HH_OK
+    assert nb.value >= 7 * 128 * 128 * 8
+    assert lib.hh_shf_workspace_size(513, 4, 3, ctypes.byref(nb)) == L.HH_ERR_UNSUPPORTED
+    assert lib.hh_shf_workspace_size(16, -1, 3, ctypes.byref(nb)) == L.HH_ERR_INVALID_ARG
+
+    def call(S=1024, lds=16, R=2048, ws=4096, wsb=1 << 22):
+        return lib.hh_shf(16, 2, 3, 1, v(S) if S else None, lds, v(R) if R else None, 16, v(6144),
+                          v(7168), None, v(ws) if ws else None, wsb, None)
+    assert call(S=0) == L.HH_ERR_INVALID_ARG
+    assert call(lds=8) == L.HH_ERR_INVALID_ARG
+    assert call(R=0) == L.HH_ERR_INVALID_ARG
+    assert call(wsb=64) == L.HH_ERR_WORKSPACE
