@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 MFMA_BF16_TFLOPS = 2500.0      # dense
+MFMA_F32_TFLOPS = 157.3        # dense FP32 matrix cores
 FP32_VALU_TFLOPS = 78.6        # unpacked FP32 FMA (packed FP32 is switched off)
 FP64_VALU_TFLOPS = 78.6
 
@@ -57,10 +58,15 @@ WORKLOADS = {
     "qr_n512_h511": ("apply_qr", 512, 511, 1 << 20, "f32",
                      "Q X with h = n - 1 reflectors of Householder QR structure (k - 1 leading "
                      "zeros, the remark after Result 3), n=512, N=2^20; fused FP32"),
+    "knn_n40_h6": ("knn", 40, 6, 49000, "f32",
+                   "k-NN (k = 5) in the learned metric, n=40, h=6, 21000 queries against 49000 "
+                   "database vectors (the sizes of the paper's MNIST split, synthetic Gaussian data): "
+                   "transform both sets, then all-pairs distances on the matrix cores and top-k"),
     "copy_n4096_bf16": ("copy", 4096, 0, 1 << 18, "bf16",
                         "device copy of the Q X batch (2 GiB in, 2 GiB out): HBM calibration"),
 }
 DEFAULT = "qx_n4096_h64"
+KNN_QUERIES, KNN_K = 21000, 5
 
 
 def parse():
@@ -94,6 +100,10 @@ def algorithmic(op, n, h, N, io_bytes, param_bytes=4):
         return 5 * n * io_bytes * N, (4 * n * h + 2 * h * h) * 4 * N
     if op == "sym_fb":     # ~24 n h per vector for forward + backward on the matrix cores
         return 5 * n * io_bytes * N, 24 * n * h * N
+    if op == "knn":        # transforms of both sets, then the all-pairs products (n padded to 4)
+        nq = KNN_QUERIES
+        npad = (n + 3) // 4 * 4
+        return (N + nq) * n * io_bytes * 2, 2 * npad * nq * N + 4 * n * h * (N + nq)
     if op == "mahal_fb":
         fwd = (2 * n * io_bytes + param_bytes) * N
         bwd = (2 * n * io_bytes + param_bytes) * N
@@ -182,6 +192,10 @@ def main():
         Gd = synth.device_gaussian((N, n), seed=0, stream=synth.STREAM_G, device=dev, dtype=io_dt)
     Y = torch.empty_like(X) if op in ("apply", "apply_qr", "sym", "sym_d", "copy", "apply_fb",
                                       "sym_fb") else None
+    Xq = None
+    if op == "knn":
+        Xq = synth.device_gaussian((KNN_QUERIES, n), seed=0, stream=synth.STREAM_XB, device=dev,
+                                   dtype=io_dt)
     dsig = None
     if op == "sym_d":
         dsig = torch.tensor(np.where(synth.host_rng(0, 11).random(n) < 0.5, -1.0, 1.0), dtype=pdt, device=dev)
@@ -200,6 +214,8 @@ def main():
             P.signed_raw("sym", U, X, d_in=dsig, d_out=dsig, lam=lam, compute=tdt, out=Y)
         elif op == "mahal":
             P.mahal_raw(U, lam, X, Xb)
+        elif op == "knn":
+            P.knn(U, lam, Xq, X, KNN_K)
         elif op == "apply_fb":  # the forward keeps its WY coefficients for the backward
             _, rec = P.apply_raw(U, X, compute=tdt, out=Y, save=True)
             P.apply_bwd_raw(U, X, Gd, compute=tdt, saved=rec)
@@ -226,7 +242,7 @@ def main():
     per = [a.elapsed_time(b) for a, b in evs]  # ms per call, on the launch stream
     ms_call = float(np.mean(per))
     ms_wall = wall * 1e3 / args.steps
-    value = N / (ms_wall * 1e-3)
+    value = (KNN_QUERIES if op == "knn" else N) / (ms_wall * 1e-3)
 
     # The main kernel's duration: a call also launches the per-call setup
     # kernels (normalisation, T), so the same call on a single vector is timed
@@ -266,7 +282,10 @@ def main():
 
     io_bytes = {"f32": 4, "f64": 8, "bf16": 2, "f16": 2}[comp]
     abytes, aflops = algorithmic(op, n, h, N, io_bytes, 8 if comp == "f64" else 4)
-    if comp in ("bf16", "f16"):
+    if op == "knn":
+        bound, peak, unit = "mfma", MFMA_F32_TFLOPS, "TFLOP/s"
+        ach = aflops / (ms_ev * 1e-3) / 1e12
+    elif comp in ("bf16", "f16"):
         bound, peak, unit, ach = "hbm", HBM_PEAK_GBS, "GB/s", abytes / (ms_ev * 1e-3) / 1e9
         if op == "sym_fb" and aflops / (MFMA_BF16_TFLOPS * 1e12) > abytes / (HBM_PEAK_GBS * 1e9):
             bound, peak, unit = "mfma", MFMA_BF16_TFLOPS, "TFLOP/s"
@@ -289,7 +308,7 @@ def main():
     out = {
         "metric": "vectors/s for Q.X at n=4096,h=64 (BF16 compact-WY vs FP32 fused)",
         "value": value,
-        "unit": "vectors/s",
+        "unit": "queries/s" if op == "knn" else "vectors/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -334,6 +353,42 @@ def main():
                             "wy_speedup": (N / (ms_wall * 1e-3)) / (N / (msf * 1e-3))}
         del Xf, Yf
         Y = None
+
+    # k-NN: the search kernel alone (transforms excluded), and the oracle on a
+    # bounded sample of queries (every pair's distance by definition, sorted)
+    if op == "knn":
+        sq = torch.sqrt(lam)
+        Zq = P.signed_raw("apply_T", U, Xq, d_out=sq)
+        Zd = P.signed_raw("apply_T", U, X, d_out=sq)
+        P.knn_raw(Zq, Zd, KNN_K)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        kf = max(1, min(args.steps, 5))
+        a.record(stream)
+        for _ in range(kf):
+            P.knn_raw(Zq, Zd, KNN_K)
+        b.record(stream)
+        torch.cuda.synchronize()
+        msk = a.elapsed_time(b) / kf
+        npad = (n + 3) // 4 * 4
+        out["knn_kernel"] = {"ms_per_call": msk, "queries": KNN_QUERIES, "database": N, "k": KNN_K,
+                             "tflops_products": 2 * npad * KNN_QUERIES * N / (msk * 1e-3) / 1e12}
+        if not args.no_cpu:
+            import oracle
+            Uh, lh = U.double().cpu().numpy(), lam.double().cpu().numpy()
+            S = 8
+            xq, xd = Xq[:S].double().cpu().numpy(), X.double().cpu().numpy()
+            t = time.perf_counter()
+            Dh = oracle.mahal(Uh, lh, np.repeat(xq, N, axis=0), np.tile(xd, (S, 1))).reshape(S, N)
+            ref = np.sort(Dh, axis=1)[:, :KNN_K]
+            tcpu = time.perf_counter() - t
+            dg, _ = P.knn(U, lam, Xq[:S], X, KNN_K)
+            dg = dg.double().cpu().numpy()
+            out["cpu_baseline"] = {"value": S / tcpu, "unit": "queries/s", "cores": oracle.num_threads(),
+                                   "kind": "oracle",
+                                   "sample": f"first {S} of {KNN_QUERIES} queries against all {N} "
+                                             "database vectors, FP64, all pairs then sort"}
+            out["max_rel_err_sample"] = float(np.max(np.abs(dg - ref) / ref))
 
     # the same reflectors through the dense kernels, timed beside
     if op == "apply_qr":

@@ -337,6 +337,22 @@ HH_API hh_status hh_shf(int64_t n, int64_t h, int64_t K, int spectrum_update, co
                         int64_t lds, double *R, int64_t ldr, double *sbar, double *d, double *err,
                         void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * k nearest neighbours in the learned metric (Sec. IV-C: new points are
+ * transformed, x <- L x with L = sqrt(Lambda) U, then k-NN runs on them).
+ * Zq (Nq transformed queries) and Zd (Nd transformed database vectors) are
+ * FP32 n-vectors (column-major, ld >= n; e.g. hh_forward_signed(HH_OP_APPLY_T,
+ * d_out = sqrt(lam)) of the raw data, so that ||z_a - z_b||^2 is the
+ * Mahalanobis distance of hh_mahalanobis).  For every query: the k smallest
+ * squared distances in ascending order into dist (Nq x k, row q contiguous)
+ * and their database indices into idx (Nq x k); equal distances keep the
+ * smaller index.  Candidates are ranked by ||a||^2 + ||b||^2 - 2 a^T b (the
+ * products on the matrix cores in FP32); the k returned distances are
+ * recomputed from the differences.  n <= 224, 1 <= k <= 32, k <= Nd. */
+HH_API hh_status hh_knn(int64_t n, int64_t Nq, int64_t Nd, int64_t k, const float *Zq, int64_t ldq,
+                        const float *Zd, int64_t ldd, float *dist, int64_t *idx,
+                        hipStream_t stream);
+
 /* Size of the static device scratch of hh_forward_noalloc (16 MiB, held by
  * each GPU the library runs on until the process ends). */
 #define HH_NOALLOC_SCRATCH_BYTES (16u << 20)

@@ -520,3 +520,29 @@ def shf(S, h, K=30, spectrum_update=True):
                                      L.ptr(R) if h else None, n, L.ptr(sbar), L.ptr(d),
                                      L.ptr(err), L.ptr(ws), ws.numel(), L.stream_of(St)))
     return R, sbar, d, err
+
+
+def knn_raw(Zq, Zd, k):
+    """k nearest database rows of Zd (Nd, n) for every query row of Zq (Nq, n)
+    in squared Euclidean distance (FP32 device tensors of transformed
+    vectors): returns (dist (Nq, k) float32 ascending, idx (Nq, k) int64)."""
+    _check_dev(Zq, Zd)
+    Zq, Zd = _rows(Zq.to(torch.float32)), _rows(Zd.to(torch.float32))
+    Nq, n = Zq.shape
+    Nd = Zd.shape[0]
+    dist = torch.empty((Nq, k), dtype=torch.float32, device=Zq.device)
+    idx = torch.empty((Nq, k), dtype=torch.int64, device=Zq.device)
+    L.check("hh_knn", L.lib().hh_knn(n, Nq, Nd, k, L.ptr(Zq), L.ld(Zq), L.ptr(Zd), L.ld(Zd),
+                                     L.ptr(dist), L.ptr(idx), L.stream_of(Zq)))
+    return dist, idx
+
+
+def knn(U, lam, Xq, Xd, k):
+    """k nearest neighbours in the learned metric d(x, y) = sum_i lam_i
+    ((Q^T (x - y))_i)^2 (Sec. IV-C): both sets are transformed by
+    L = diag(sqrt(lam)) Q^T on the fused kernels (one pass each), then
+    knn_raw runs on the transformed vectors."""
+    sq = torch.sqrt(lam.to(torch.float32))
+    Zq = signed_raw("apply_T", U, Xq.to(torch.float32), d_out=sq)
+    Zd = signed_raw("apply_T", U, Xd.to(torch.float32), d_out=sq)
+    return knn_raw(Zq, Zd, k)

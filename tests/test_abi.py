@@ -303,3 +303,19 @@ def test_shf_validation():
     assert call(lds=8) == L.HH_ERR_INVALID_ARG
     assert call(R=0) == L.HH_ERR_INVALID_ARG
     assert call(wsb=64) == L.HH_ERR_WORKSPACE
+
+
+def test_knn_validation():
+    v = ctypes.c_void_p
+    lib = P.lib()
+
+    def call(n=8, Nq=4, Nd=10, k=3, ldq=8, ldd=8, ptr=1024):
+        p = v(ptr) if ptr else None
+        return lib.hh_knn(n, Nq, Nd, k, p, ldq, p, ldd, p, p, None)
+    assert call(k=0) == L.HH_ERR_INVALID_ARG
+    assert call(k=11) == L.HH_ERR_INVALID_ARG      # k > Nd
+    assert call(k=33, Nd=100) == L.HH_ERR_UNSUPPORTED
+    assert call(n=225, ldq=225, ldd=225) == L.HH_ERR_UNSUPPORTED
+    assert call(ldq=7) == L.HH_ERR_INVALID_ARG
+    assert call(ptr=0) == L.HH_ERR_INVALID_ARG
+    assert call(Nq=0, ptr=0) == L.HH_OK
