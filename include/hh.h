@@ -348,10 +348,13 @@ HH_API hh_status hh_shf(int64_t n, int64_t h, int64_t K, int spectrum_update, co
  * and their database indices into idx (Nq x k); equal distances keep the
  * smaller index.  Candidates are ranked by ||a||^2 + ||b||^2 - 2 a^T b (the
  * products on the matrix cores in FP32); the k returned distances are
- * recomputed from the differences.  n <= 224, 1 <= k <= 32, k <= Nd. */
+ * recomputed from the differences.  n <= 224, 1 <= k <= 32, k <= Nd; a
+ * workspace of hh_knn_workspace_size bytes holds the per-split lists. */
+HH_API hh_status hh_knn_workspace_size(int64_t n, int64_t Nq, int64_t Nd, int64_t k,
+                                       size_t *bytes);
 HH_API hh_status hh_knn(int64_t n, int64_t Nq, int64_t Nd, int64_t k, const float *Zq, int64_t ldq,
-                        const float *Zd, int64_t ldd, float *dist, int64_t *idx,
-                        hipStream_t stream);
+                        const float *Zd, int64_t ldd, float *dist, int64_t *idx, void *ws,
+                        size_t ws_bytes, hipStream_t stream);
 
 /* Size of the static device scratch of hh_forward_noalloc (16 MiB, held by
  * each GPU the library runs on until the process ends). */

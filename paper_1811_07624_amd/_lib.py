@@ -25,7 +25,8 @@ EXPORTS = (
     "hh_apply_backward", "hh_apply_T_backward", "hh_sym_apply_backward",
     "hh_mahalanobis_backward", "hh_saved_size", "hh_forward_save", "hh_backward_saved",
     "hh_forward_signed", "hh_backward_signed", "hh_forward_noalloc", "hh_factor_workspace_size",
-    "hh_factor_orthonormal", "hh_shf_workspace_size", "hh_shf", "hh_knn", "hh_status_string",
+    "hh_factor_orthonormal", "hh_shf_workspace_size", "hh_shf", "hh_knn_workspace_size", "hh_knn",
+    "hh_status_string",
     "hh_last_error", "hh_version",
 )
 HH_FACTOR_CONSTRAINED, HH_FACTOR_UNCONSTRAINED, HH_FACTOR_QR = range(3)
@@ -85,7 +86,8 @@ def lib():
         "hh_factor_orthonormal": [ctypes.c_int, I, I, P, I, P, I, P, P, P, S, P],
         "hh_shf_workspace_size": [I, I, I, ctypes.POINTER(S)],
         "hh_shf": [I, I, I, ctypes.c_int, P, I, P, I, P, P, P, P, S, P],
-        "hh_knn": [I, I, I, I, P, I, P, I, P, P, P],
+        "hh_knn_workspace_size": [I, I, I, I, ctypes.POINTER(S)],
+        "hh_knn": [I, I, I, I, P, I, P, I, P, P, P, S, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)

@@ -7,15 +7,19 @@
 // the products a_i^T b_j on the matrix cores (v_mfma_f32_16x16x4_f32, full
 // FP32), then for every query the k smallest d_ij and their database indices.
 //
-// A workgroup (4 waves) owns 64 queries, staged once in LDS, and streams the
-// database through LDS in tiles of 64 vectors; each wave forms a 32 x 32 block
-// of the 64 x 64 product tile (four 16 x 16 MFMA blocks, K = 4 per step).  The
-// distance tile goes through LDS, where one thread per query keeps its k best
-// in ascending order (a candidate enters only when strictly below the current
-// k-th, so among equal distances the earlier database index stays).  The
-// expanded form loses accuracy through cancellation when d_ij is small next
-// to ||a||^2 + ||b||^2, so the k survivors' distances are recomputed from the
+// A workgroup (4 waves) owns 64 queries, staged once in LDS, and streams one
+// split of the database through LDS in tiles of 64 vectors (the splits give
+// the chip several workgroups per compute unit); each wave forms a 32 x 32
+// block of the 64 x 64 product tile (four 16 x 16 MFMA blocks, K = 4 per
+// step).  The distance tile goes through LDS, where all threads screen it
+// against each query's current k-th distance and one thread per query inserts
+// the survivors into its sorted k best (a candidate enters only when strictly
+// below the k-th, so among equal distances the earlier index stays).  A second
+// kernel merges the splits' lists per query by (distance, index).  The
+// expanded form loses accuracy through cancellation when d_ij is small next to
+// ||a||^2 + ||b||^2, so the k survivors' distances are recomputed from the
 // differences and re-sorted before they are written.
+#include <algorithm>
 #include <cmath>
 
 #include "hh_internal.h"
@@ -32,16 +36,19 @@ constexpr int kMaxNk = 224;  // keeps the LDS tiles within 160 KB at k = 32
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // LDS: queries [kQB][np+1], database tile [kDB][np+1], distance tile
-// [kQB][kDB+1], query norms, tile norms, the k best per query (dist, index).
+// [kQB][kDB+1], query norms, tile norms, the k best per query (dist, index),
+// the current k-th distance per query and the survivor masks.
 __host__ __device__ inline size_t knn_lds(int np, int k) {
     return ((size_t)kQB * (np + 1) + (size_t)kDB * (np + 1) + (size_t)kQB * (kDB + 1) + kQB + kDB) * 4 +
-           (size_t)kQB * k * 8;
+           (size_t)kQB * k * 8 + (size_t)kQB * 4 + (size_t)kQB * 4 * 4;
 }
 
+// Split s of the database (tiles [t0, t1)) against 64 queries: the k best by
+// the expanded form, into part_d / part_i (row (s * Nq + q) * k).
 __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64_t ldq, int64_t Nq,
                                             const float *__restrict__ Zd, int64_t ldd, int64_t Nd,
-                                            int n, int np, int k, float *__restrict__ dist,
-                                            int64_t *__restrict__ idx) {
+                                            int n, int np, int k, int64_t tiles_per_split,
+                                            float *__restrict__ part_d, int *__restrict__ part_i) {
     extern __shared__ __align__(16) float sm[];
     const int sq = np + 1;
     float *sQ = sm;                              // [kQB][sq]
@@ -51,9 +58,12 @@ __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64
     float *sDn = sQn + kQB;                      // [kDB]
     float *sBd = sDn + kDB;                      // [kQB][k] best distances
     int *sBi = reinterpret_cast<int *>(sBd + kQB * k);  // [kQB][k] database indices
+    float *sKth = reinterpret_cast<float *>(sBi + kQB * k);  // [kQB]
+    unsigned *sMask = reinterpret_cast<unsigned *>(sKth + kQB);  // [kQB][4] survivors
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t q0 = (int64_t)blockIdx.x * kQB;
+    const int split = blockIdx.y;
     // queries into LDS (zero rows past Nq and columns past n)
     for (int e = tid; e < kQB * np; e += kKT) {
         const int r = e / np, c = e % np;
@@ -68,15 +78,17 @@ __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64
             sBd[tid * k + j] = INFINITY;
             sBi[tid * k + j] = -1;
         }
+        sKth[tid] = INFINITY;
     }
-    float kth = INFINITY;  // current k-th best of query tid (tid < kQB)
     // wave w: rows 32 (w / 2) .. +31, columns 32 (w % 2) .. +31 of the tile
     const int rb = 32 * (wv >> 1), cbk = 32 * (wv & 1);
     const int r16 = lane & 15, kk = lane >> 4;
     const int64_t ntiles = (Nd + kDB - 1) / kDB;
-    for (int64_t t = 0; t < ntiles; ++t) {
+    const int64_t t0 = split * tiles_per_split;
+    const int64_t t1 = t0 + tiles_per_split < ntiles ? t0 + tiles_per_split : ntiles;
+    for (int64_t t = t0; t < t1; ++t) {
         const int64_t j0 = t * kDB;
-        __syncthreads();  // previous tile's sD / sT readers are done
+        __syncthreads();  // previous tile's sD / sT / sMask readers are done
         for (int e = tid; e < kDB * np; e += kKT) {
             const int r = e / np, c = e % np;
             sD[r * sq + c] = (j0 + r < Nd && c < n) ? Zd[(j0 + r) * ldd + c] : 0.f;
@@ -118,12 +130,27 @@ __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64
                     sT[qr * (kDB + 1) + dc] = j0 + dc < Nd ? fmaxf(d, 0.f) : INFINITY;
                 }
         __syncthreads();
-        if (tid < kQB) {
+        // every thread screens 16 candidates of one query against its k-th
+        {
+            const int r = tid >> 2, c0 = 16 * (tid & 3);
+            const float kt = sKth[r];
+            unsigned m = 0;
+            for (int c = 0; c < 16; ++c)
+                if (sT[r * (kDB + 1) + c0 + c] < kt) m |= 1u << c;
+            sMask[r * 4 + (tid & 3)] = m;
+        }
+        __syncthreads();
+        if (tid < kQB) {  // the owner inserts the survivors in database order
             float *bd = sBd + tid * k;
             int *bi = sBi + tid * k;
-            for (int c = 0; c < kDB; ++c) {
-                const float d = sT[tid * (kDB + 1) + c];
-                if (d < kth) {  // insert, keeping ascending order
+            float kth = sKth[tid];
+            for (int part = 0; part < 4; ++part) {
+                unsigned m = sMask[tid * 4 + part];
+                while (m) {
+                    const int c = 16 * part + __builtin_ctz(m);
+                    m &= m - 1;
+                    const float d = sT[tid * (kDB + 1) + c];
+                    if (!(d < kth)) continue;
                     int p = k - 1;
                     while (p > 0 && bd[p - 1] > d) {
                         bd[p] = bd[p - 1];
@@ -135,40 +162,95 @@ __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64
                     kth = bd[k - 1];
                 }
             }
+            sKth[tid] = kth;
         }
     }
     __syncthreads();
-    // exact distances of the survivors from the differences, re-sorted
     if (tid < kQB && q0 + tid < Nq) {
-        float *bd = sBd + tid * k;
-        int *bi = sBi + tid * k;
+        const int64_t row = ((int64_t)split * Nq + q0 + tid) * k;
         for (int j = 0; j < k; ++j) {
-            if (bi[j] < 0) continue;
-            const float *b = Zd + (int64_t)bi[j] * ldd;
-            float s = 0.f;
-            for (int c = 0; c < n; ++c) {
-                const float r = sQ[tid * sq + c] - b[c];
-                s = fmaf(r, r, s);
-            }
-            bd[j] = s;
-        }
-        for (int j = 1; j < k; ++j) {  // insertion sort by (distance, index)
-            const float d = bd[j];
-            const int x = bi[j];
-            int p = j;
-            while (p > 0 && (bd[p - 1] > d || (bd[p - 1] == d && (unsigned)bi[p - 1] > (unsigned)x))) {
-                bd[p] = bd[p - 1];
-                bi[p] = bi[p - 1];
-                --p;
-            }
-            bd[p] = d;
-            bi[p] = x;
-        }
-        for (int j = 0; j < k; ++j) {
-            dist[(q0 + tid) * k + j] = bd[j];
-            idx[(q0 + tid) * k + j] = bi[j];
+            part_d[row + j] = sBd[tid * k + j];
+            part_i[row + j] = sBi[tid * k + j];
         }
     }
+}
+
+// One thread per query: merge the S split lists (each ascending, ties by
+// index) by (distance, index), recompute the k survivors' distances from the
+// differences, re-sort and write.
+__global__ __launch_bounds__(256) void k_knn_merge(const float *__restrict__ Zq, int64_t ldq,
+                                                  int64_t Nq, const float *__restrict__ Zd,
+                                                  int64_t ldd, int n, int k, int S,
+                                                  const float *__restrict__ part_d,
+                                                  const int *__restrict__ part_i,
+                                                  float *__restrict__ dist, int64_t *__restrict__ idx) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= Nq) return;
+    float bd[kMaxK];
+    int bi[kMaxK];
+    int pos[16];
+    for (int s = 0; s < S; ++s) pos[s] = 0;
+    for (int j = 0; j < k; ++j) {
+        int best = -1;
+        float bdv = INFINITY;
+        int biv = 0x7fffffff;
+        for (int s = 0; s < S; ++s) {
+            if (pos[s] >= k) continue;
+            const int64_t r = ((int64_t)s * Nq + q) * k + pos[s];
+            const int x = part_i[r];
+            if (x < 0) continue;
+            const float d = part_d[r];
+            if (d < bdv || (d == bdv && x < biv)) {
+                bdv = d;
+                biv = x;
+                best = s;
+            }
+        }
+        bd[j] = bdv;
+        bi[j] = best < 0 ? -1 : biv;
+        if (best >= 0) ++pos[best];
+    }
+    const float *a = Zq + q * ldq;
+    for (int j = 0; j < k; ++j) {
+        if (bi[j] < 0) continue;
+        const float *b = Zd + (int64_t)bi[j] * ldd;
+        float s = 0.f;
+        for (int c = 0; c < n; ++c) {
+            const float r = a[c] - b[c];
+            s = fmaf(r, r, s);
+        }
+        bd[j] = s;
+    }
+    for (int j = 1; j < k; ++j) {  // insertion sort by (distance, index)
+        const float d = bd[j];
+        const int x = bi[j];
+        int p = j;
+        while (p > 0 && (bd[p - 1] > d || (bd[p - 1] == d && (unsigned)bi[p - 1] > (unsigned)x))) {
+            bd[p] = bd[p - 1];
+            bi[p] = bi[p - 1];
+            --p;
+        }
+        bd[p] = d;
+        bi[p] = x;
+    }
+    for (int j = 0; j < k; ++j) {
+        dist[q * k + j] = bd[j];
+        idx[q * k + j] = bi[j];
+    }
+}
+
+// Database splits: enough workgroups to fill the chip (about four per
+// compute unit), at most 16 splits, at least 4 tiles per split.
+int knn_splits(int64_t Nq, int64_t Nd) {
+    const int64_t qb = (Nq + kQB - 1) / kQB, ntiles = (Nd + kDB - 1) / kDB;
+    int64_t s = (4 * (int64_t)device_cu_count() + qb - 1) / qb;
+    s = std::min<int64_t>(s, 16);
+    s = std::min<int64_t>(s, std::max<int64_t>(1, ntiles / 4));
+    return (int)std::max<int64_t>(1, s);
+}
+
+size_t knn_ws_bytes(int64_t Nq, int64_t k, int S) {
+    return align256((size_t)S * Nq * k * 4) * 2;
 }
 
 }  // namespace
@@ -178,23 +260,48 @@ using namespace hh;
 
 extern "C" {
 
-hh_status hh_knn(int64_t n, int64_t Nq, int64_t Nd, int64_t k, const float *Zq, int64_t ldq,
-                 const float *Zd, int64_t ldd, float *dist, int64_t *idx, hipStream_t st) {
+static hh_status knn_check(int64_t n, int64_t Nq, int64_t Nd, int64_t k) {
     if (n < 1 || Nq < 0 || Nd < 0 || k < 1)
         return set_error(HH_ERR_INVALID_ARG, "need n >= 1, Nq >= 0, Nd >= 0, k >= 1");
     if (n > kMaxNk || k > kMaxK)
         return set_error(HH_ERR_UNSUPPORTED, "k-NN supports n <= %d and k <= %d", kMaxNk, kMaxK);
-    if (Nd > ((int64_t)1 << 31) - 1) return set_error(HH_ERR_UNSUPPORTED, "Nd must be < 2^31");
+    if (Nd > ((int64_t)1 << 31) - 1 || Nq > ((int64_t)1 << 36))
+        return set_error(HH_ERR_UNSUPPORTED, "Nd must be < 2^31");
     if (k > Nd) return set_error(HH_ERR_INVALID_ARG, "k = %lld exceeds Nd = %lld", (long long)k, (long long)Nd);
+    return HH_OK;
+}
+
+hh_status hh_knn_workspace_size(int64_t n, int64_t Nq, int64_t Nd, int64_t k, size_t *bytes) {
+    if (!bytes) return set_error(HH_ERR_INVALID_ARG, "bytes must not be null");
+    const hh_status s = knn_check(n, Nq, Nd, k);
+    if (s != HH_OK) return s;
+    *bytes = Nq == 0 ? 0 : knn_ws_bytes(Nq, k, knn_splits(Nq, Nd));
+    return HH_OK;
+}
+
+hh_status hh_knn(int64_t n, int64_t Nq, int64_t Nd, int64_t k, const float *Zq, int64_t ldq,
+                 const float *Zd, int64_t ldd, float *dist, int64_t *idx, void *ws, size_t ws_bytes,
+                 hipStream_t st) {
+    const hh_status s = knn_check(n, Nq, Nd, k);
+    if (s != HH_OK) return s;
     if (ldq < n || ldd < n) return set_error(HH_ERR_INVALID_ARG, "leading dimensions must be >= n");
     if (Nq == 0) return HH_OK;
-    if (!Zq || !Zd || !dist || !idx) return set_error(HH_ERR_INVALID_ARG, "pointers must not be null");
+    if (!Zq || !Zd || !dist || !idx || !ws) return set_error(HH_ERR_INVALID_ARG, "pointers must not be null");
+    const int S = knn_splits(Nq, Nd);
+    const size_t need = knn_ws_bytes(Nq, k, S);
+    if (ws_bytes < need) return set_error(HH_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", need, ws_bytes);
     const int np = (int)((n + 3) / 4 * 4);
     const size_t lds = knn_lds(np, (int)k);
-    const int64_t blocks = (Nq + kQB - 1) / kQB;
-    if (blocks > ((int64_t)1 << 31) - 1) return set_error(HH_ERR_UNSUPPORTED, "too many queries");
-    hipLaunchKernelGGL(k_knn, dim3((unsigned)blocks), dim3(kKT), lds, st, Zq, ldq, Nq, Zd, ldd, Nd,
-                       (int)n, np, (int)k, dist, idx);
+    const int64_t qblocks = (Nq + kQB - 1) / kQB;
+    if (qblocks > ((int64_t)1 << 31) - 1) return set_error(HH_ERR_UNSUPPORTED, "too many queries");
+    const int64_t ntiles = (Nd + kDB - 1) / kDB;
+    const int64_t tps = (ntiles + S - 1) / S;
+    float *pd = static_cast<float *>(ws);
+    int *pi = reinterpret_cast<int *>(static_cast<char *>(ws) + align256((size_t)S * Nq * k * 4));
+    hipLaunchKernelGGL(k_knn, dim3((unsigned)qblocks, (unsigned)S), dim3(kKT), lds, st, Zq, ldq, Nq, Zd,
+                       ldd, Nd, (int)n, np, (int)k, tps, pd, pi);
+    hipLaunchKernelGGL(k_knn_merge, dim3((unsigned)((Nq + 255) / 256)), dim3(256), 0, st, Zq, ldq, Nq, Zd,
+                       ldd, (int)n, (int)k, S, pd, pi, dist, idx);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? HH_OK : set_error(HH_ERR_HIP, "k-NN launch: %s", hipGetErrorString(e));
 }

@@ -532,8 +532,11 @@ def knn_raw(Zq, Zd, k):
     Nd = Zd.shape[0]
     dist = torch.empty((Nq, k), dtype=torch.float32, device=Zq.device)
     idx = torch.empty((Nq, k), dtype=torch.int64, device=Zq.device)
+    nb = ctypes.c_size_t(0)
+    L.check("hh_knn_workspace_size", L.lib().hh_knn_workspace_size(n, Nq, Nd, k, ctypes.byref(nb)))
+    ws = torch.empty((max(nb.value, 1),), dtype=torch.uint8, device=Zq.device)
     L.check("hh_knn", L.lib().hh_knn(n, Nq, Nd, k, L.ptr(Zq), L.ld(Zq), L.ptr(Zd), L.ld(Zd),
-                                     L.ptr(dist), L.ptr(idx), L.stream_of(Zq)))
+                                     L.ptr(dist), L.ptr(idx), L.ptr(ws), ws.numel(), L.stream_of(Zq)))
     return dist, idx
 
 

@@ -309,9 +309,10 @@ def test_knn_validation():
     v = ctypes.c_void_p
     lib = P.lib()
 
-    def call(n=8, Nq=4, Nd=10, k=3, ldq=8, ldd=8, ptr=1024):
+    def call(n=8, Nq=4, Nd=10, k=3, ldq=8, ldd=8, ptr=1024, wsb=1 << 20):
         p = v(ptr) if ptr else None
-        return lib.hh_knn(n, Nq, Nd, k, p, ldq, p, ldd, p, p, None)
+        return lib.hh_knn(n, Nq, Nd, k, p, ldq, p, ldd, p, p, p, wsb, None)
+    assert call(wsb=8) == L.HH_ERR_WORKSPACE
     assert call(k=0) == L.HH_ERR_INVALID_ARG
     assert call(k=11) == L.HH_ERR_INVALID_ARG      # k > Nd
     assert call(k=33, Nd=100) == L.HH_ERR_UNSUPPORTED
