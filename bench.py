@@ -119,20 +119,20 @@ def source_hash(paths):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_key, src_paths):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+def measured_traffic(workload):
+    """HBM bytes per launch of the workload's dominant kernel from the committed
+    rocprofv3 counter summary, if the counters were taken on the current
+    sources of that kernel (the entry lists them with their hash); else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     try:
         with open(p) as f:
-            table = json.load(f)
-        e = table.get(kernel_key)
-        if not e or e.get("source_hash") != source_hash(src_paths):
+            e = json.load(f).get(workload)
+        if not e or e.get("source_hash") != source_hash(e["sources"]):
             return None
         return e.get("bytes_per_launch")
-    except Exception:
+    except (OSError, ValueError, KeyError):
         return None
 
 
@@ -299,11 +299,7 @@ def main():
         else:
             bound, peak, unit = "hbm", HBM_PEAK_GBS, "GB/s"
             ach = abytes / (ms_ev * 1e-3) / 1e9
-    wy_src = ["paper_1811_07624_amd/csrc/hh_wy.hip", "paper_1811_07624_amd/csrc/hh_wy_common.h",
-              "paper_1811_07624_amd/csrc/hh_internal.h"]
-    kernel_src = {"bf16": wy_src, "f16": wy_src}.get(
-        comp, ["paper_1811_07624_amd/csrc/hh_fused.hip", "paper_1811_07624_amd/csrc/hh_internal.h"])
-    traffic = measured_traffic(args.workload, kernel_src)
+    traffic = measured_traffic(args.workload)
 
     out = {
         "metric": "vectors/s for Q.X at n=4096,h=64 (BF16 compact-WY vs FP32 fused)",
