@@ -528,6 +528,19 @@ __global__ __launch_bounds__(kThreadsWY, 2 * MINB) void k_wy_fwd(WyArgs a) {
         return v;
     };
     v8 xr[P][CB];
+    // Every block alternates a compute phase (no HBM access) with an HBM
+    // phase (the tile's stores, then the next tile's loads).  Started together,
+    // the blocks stay in step, so HBM idles during the compute phases and is
+    // oversubscribed during the HBM phases.  With many tiles per block, the
+    // blocks of each XCD (dispatched round-robin over the 8 XCDs) start at 16
+    // staggered times, spread over about two tile periods, so that the HBM
+    // phases of different compute units overlap other units' products.
+    {
+        const int64_t per_block = ntiles / gridDim.x;
+        const int units = per_block < 4 ? 0 : (int)std::min<int64_t>(30, per_block - 2);
+        const int ph = (blockIdx.x >> 3) & 15;
+        for (int i = 0; i < ph * units / 15; ++i) __builtin_amdgcn_s_sleep(127);
+    }
     if ((int64_t)blockIdx.x < ntiles) {
         const __amdgpu_buffer_rsrc_t rX0 = tile_rsrc(blockIdx.x, X, a.ldx);
 #pragma unroll
