@@ -322,6 +322,9 @@ def main():
                      "setup_ms_events": ms_setup, "algorithmic_bytes": abytes,
                      "algorithmic_flops": aflops},
     }
+    if bound == "alu" and comp == "f32":  # the same rate against the FP32 matrix cores
+        out["roofline"]["peak_fp32_matrix"] = MFMA_F32_TFLOPS
+        out["roofline"]["frac_fp32_matrix"] = ach / MFMA_F32_TFLOPS
 
     # orthogonality of the operator the path applies: Q (and Q^T) applied to
     # the identity (exact in every compute type) at this workload's n and h,
