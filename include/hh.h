@@ -349,7 +349,8 @@ HH_API hh_status hh_shf(int64_t n, int64_t h, int64_t K, int spectrum_update, co
  * smaller index.  Candidates are ranked by ||a||^2 + ||b||^2 - 2 a^T b (the
  * products on the matrix cores in FP32); the k returned distances are
  * recomputed from the differences.  n <= 224, 1 <= k <= 32, k <= Nd; a
- * workspace of hh_knn_workspace_size bytes holds the per-split lists. */
+ * workspace of hh_knn_workspace_size bytes holds the per-split lists and the
+ * squared norms of both sets. */
 HH_API hh_status hh_knn_workspace_size(int64_t n, int64_t Nq, int64_t Nd, int64_t k,
                                        size_t *bytes);
 HH_API hh_status hh_knn(int64_t n, int64_t Nq, int64_t Nd, int64_t k, const float *Zq, int64_t ldq,

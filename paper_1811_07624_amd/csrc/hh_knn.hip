@@ -7,9 +7,12 @@
 // the products a_i^T b_j on the matrix cores (v_mfma_f32_16x16x4_f32, full
 // FP32), then for every query the k smallest d_ij and their database indices.
 //
-// A workgroup (4 waves) owns 64 queries, staged once in LDS, and streams one
-// split of the database through LDS in tiles of 64 vectors (the splits give
-// the chip several workgroups per compute unit); each wave forms a 32 x 32
+// A first kernel forms every ||a_i||^2 and ||b_j||^2 (one thread per vector,
+// FP32 FMAs in coordinate order).  A workgroup (4 waves) owns 64 queries,
+// staged once in LDS, and streams one split of the database through LDS in
+// tiles of 64 vectors (the splits give the chip several workgroups per
+// compute unit);
+// each wave forms a 32 x 32
 // block of the 64 x 64 product tile (four 16 x 16 MFMA blocks, K = 4 per
 // step).  The distance tile goes through LDS, where all threads screen it
 // against each query's current k-th distance and one thread per query inserts
@@ -43,10 +46,22 @@ __host__ __device__ inline size_t knn_lds(int np, int k) {
            (size_t)kQB * k * 8 + (size_t)kQB * 4 + (size_t)kQB * 4 * 4;
 }
 
+// Squared norms of the N vectors of Z (FP32 FMAs in coordinate order).
+__global__ __launch_bounds__(256) void k_knn_norms(const float *__restrict__ Z, int64_t ld, int64_t N, int n,
+                                                  float *__restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= N) return;
+    const float *z = Z + j * ld;
+    float s = 0.f;
+    for (int c = 0; c < n; ++c) s = fmaf(z[c], z[c], s);
+    out[j] = s;
+}
+
 // Split s of the database (tiles [t0, t1)) against 64 queries: the k best by
 // the expanded form, into part_d / part_i (row (s * Nq + q) * k).
 __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64_t ldq, int64_t Nq,
                                             const float *__restrict__ Zd, int64_t ldd, int64_t Nd,
+                                            const float *__restrict__ qnorm, const float *__restrict__ dnorm,
                                             int n, int np, int k, int64_t tiles_per_split,
                                             float *__restrict__ part_d, int *__restrict__ part_i) {
     extern __shared__ __align__(16) float sm[];
@@ -71,9 +86,7 @@ __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64
     }
     __syncthreads();
     if (tid < kQB) {
-        float s = 0.f;
-        for (int c = 0; c < n; ++c) s = fmaf(sQ[tid * sq + c], sQ[tid * sq + c], s);
-        sQn[tid] = s;
+        sQn[tid] = q0 + tid < Nq ? qnorm[q0 + tid] : 0.f;
         for (int j = 0; j < k; ++j) {
             sBd[tid * k + j] = INFINITY;
             sBi[tid * k + j] = -1;
@@ -93,12 +106,8 @@ __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64
             const int r = e / np, c = e % np;
             sD[r * sq + c] = (j0 + r < Nd && c < n) ? Zd[(j0 + r) * ldd + c] : 0.f;
         }
+        if (tid < kDB) sDn[tid] = j0 + tid < Nd ? dnorm[j0 + tid] : 0.f;
         __syncthreads();
-        if (tid < kDB) {
-            float s = 0.f;
-            for (int c = 0; c < n; ++c) s = fmaf(sD[tid * sq + c], sD[tid * sq + c], s);
-            sDn[tid] = s;
-        }
         f32x4 acc[2][2];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -116,7 +125,6 @@ __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64
                 for (int b = 0; b < 2; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
-        __syncthreads();  // sDn ready
         // distance tile: acc[a][b][i] is the product of query rb + 16 a + 4 kk + i
         // and database vector cbk + 16 b + r16
 #pragma unroll
@@ -249,8 +257,9 @@ int knn_splits(int64_t Nq, int64_t Nd) {
     return (int)std::max<int64_t>(1, s);
 }
 
-size_t knn_ws_bytes(int64_t Nq, int64_t k, int S) {
-    return align256((size_t)S * Nq * k * 4) * 2;
+// per-split lists (distances, indices), then the query and database norms
+size_t knn_ws_bytes(int64_t Nq, int64_t Nd, int64_t k, int S) {
+    return align256((size_t)S * Nq * k * 4) * 2 + align256((size_t)Nq * 4) + align256((size_t)Nd * 4);
 }
 
 }  // namespace
@@ -275,7 +284,7 @@ hh_status hh_knn_workspace_size(int64_t n, int64_t Nq, int64_t Nd, int64_t k, si
     if (!bytes) return set_error(HH_ERR_INVALID_ARG, "bytes must not be null");
     const hh_status s = knn_check(n, Nq, Nd, k);
     if (s != HH_OK) return s;
-    *bytes = Nq == 0 ? 0 : knn_ws_bytes(Nq, k, knn_splits(Nq, Nd));
+    *bytes = Nq == 0 ? 0 : knn_ws_bytes(Nq, Nd, k, knn_splits(Nq, Nd));
     return HH_OK;
 }
 
@@ -288,7 +297,7 @@ hh_status hh_knn(int64_t n, int64_t Nq, int64_t Nd, int64_t k, const float *Zq, 
     if (Nq == 0) return HH_OK;
     if (!Zq || !Zd || !dist || !idx || !ws) return set_error(HH_ERR_INVALID_ARG, "pointers must not be null");
     const int S = knn_splits(Nq, Nd);
-    const size_t need = knn_ws_bytes(Nq, k, S);
+    const size_t need = knn_ws_bytes(Nq, Nd, k, S);
     if (ws_bytes < need) return set_error(HH_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", need, ws_bytes);
     const int np = (int)((n + 3) / 4 * 4);
     const size_t lds = knn_lds(np, (int)k);
@@ -296,10 +305,18 @@ hh_status hh_knn(int64_t n, int64_t Nq, int64_t Nd, int64_t k, const float *Zq, 
     if (qblocks > ((int64_t)1 << 31) - 1) return set_error(HH_ERR_UNSUPPORTED, "too many queries");
     const int64_t ntiles = (Nd + kDB - 1) / kDB;
     const int64_t tps = (ntiles + S - 1) / S;
-    float *pd = static_cast<float *>(ws);
-    int *pi = reinterpret_cast<int *>(static_cast<char *>(ws) + align256((size_t)S * Nq * k * 4));
+    char *w = static_cast<char *>(ws);
+    const size_t lb = align256((size_t)S * Nq * k * 4);
+    float *pd = reinterpret_cast<float *>(w);
+    int *pi = reinterpret_cast<int *>(w + lb);
+    float *qn = reinterpret_cast<float *>(w + 2 * lb);
+    float *dn = reinterpret_cast<float *>(w + 2 * lb + align256((size_t)Nq * 4));
+    hipLaunchKernelGGL(k_knn_norms, dim3((unsigned)((Nq + 255) / 256)), dim3(256), 0, st, Zq, ldq, Nq, (int)n, qn);
+    if (Nd > 0)
+        hipLaunchKernelGGL(k_knn_norms, dim3((unsigned)((Nd + 255) / 256)), dim3(256), 0, st, Zd, ldd, Nd, (int)n,
+                           dn);
     hipLaunchKernelGGL(k_knn, dim3((unsigned)qblocks, (unsigned)S), dim3(kKT), lds, st, Zq, ldq, Nq, Zd,
-                       ldd, Nd, (int)n, np, (int)k, tps, pd, pi);
+                       ldd, Nd, qn, dn, (int)n, np, (int)k, tps, pd, pi);
     hipLaunchKernelGGL(k_knn_merge, dim3((unsigned)((Nq + 255) / 256)), dim3(256), 0, st, Zq, ldq, Nq, Zd,
                        ldd, (int)n, (int)k, S, pd, pi, dist, idx);
     const hipError_t e = hipGetLastError();

@@ -197,11 +197,22 @@ struct GramArgs {
 };
 
 // out[pair][s][k][l] = sum over the vectors j of split s of P[k][j] Q[l][j].
+// Each 32-vector step stages the HP x 32 slices of P and Q in LDS once (one
+// 16-byte load per thread and matrix, fetched a step ahead into registers),
+// and the 8 waves read their MFMA fragments from there (each fragment crosses
+// the global read path once per block instead of once per wave): wave w forms
+// the NBW = HB*HB/8 output blocks (kb0, lb0 + i), i < NBW, w NBW = kb0 HB + lb0.
 template <typename E, int HB>
 __global__ __launch_bounds__(kT) void k_wy_cgram(GramArgs a) {
     using el = typename E::elem;
     using v8 = typename E::vec8;
     constexpr int HP = 16 * HB;
+    constexpr int NW = kT / 64;
+    constexpr int NBW = HB * HB / NW;  // output blocks per wave
+    constexpr int RS = 32 + 8;         // LDS row stride (elements): fragment reads spread over the banks
+    constexpr int NLD = HP * 4;        // 16-byte pieces per matrix slice
+    static_assert(NBW >= 1 && (HB * HB) % NW == 0, "block split");
+    __shared__ __align__(16) el sP[2][HP * RS], sQ[2][HP * RS];
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6, c = lane & 15, g = lane >> 4;
     const int pair = blockIdx.y;
@@ -209,25 +220,42 @@ __global__ __launch_bounds__(kT) void k_wy_cgram(GramArgs a) {
     const int64_t je = jb + a.chunk < a.N ? jb + a.chunk : a.N;
     const el *Pm = static_cast<const el *>(a.P[pair]);
     const el *Qm = static_cast<const el *>(a.Q[pair]);
-    for (int kb = w; kb < HB; kb += kT / 64) {
-        f32x4 acc[HB];
-#pragma unroll
-        for (int lb = 0; lb < HB; ++lb) acc[lb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int64_t j0 = jb; j0 < je; j0 += 32) {
-            // pad columns past N are zero in the coefficient buffers
-            const v8 afr = *reinterpret_cast<const v8 *>(Pm + (int64_t)(16 * kb + c) * a.ldc + j0 + 8 * g);
-#pragma unroll
-            for (int lb = 0; lb < HB; ++lb) {
-                const v8 bfr = *reinterpret_cast<const v8 *>(Qm + (int64_t)(16 * lb + c) * a.ldc + j0 + 8 * g);
-                acc[lb] = E::mfma(afr, bfr, acc[lb]);
-            }
+    // piece tid of a slice: row tid / 4, columns 8 (tid % 4) .. + 7
+    const bool ld = tid < NLD;
+    const int lr = tid >> 2, lc = 8 * (tid & 3);
+    v8 rp{}, rq{};
+    auto fetch = [&](int64_t j0) {  // pad columns past N are zero in the coefficient buffers
+        if (ld) {
+            rp = *reinterpret_cast<const v8 *>(Pm + (int64_t)lr * a.ldc + j0 + lc);
+            rq = *reinterpret_cast<const v8 *>(Qm + (int64_t)lr * a.ldc + j0 + lc);
         }
-        float *o = a.out + ((size_t)pair * gridDim.x + blockIdx.x) * HP * HP;
+    };
+    f32x4 acc[NBW];
 #pragma unroll
-        for (int lb = 0; lb < HB; ++lb)
+    for (int i = 0; i < NBW; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int kb0 = (w * NBW) / HB, lb0 = (w * NBW) % HB;  // the wave's blocks: (kb0, lb0 + i)
+    if (jb < je) fetch(jb);
+    int buf = 0;
+    for (int64_t j0 = jb; j0 < je; j0 += 32) {
+        if (ld) {
+            *reinterpret_cast<v8 *>(&sP[buf][lr * RS + lc]) = rp;
+            *reinterpret_cast<v8 *>(&sQ[buf][lr * RS + lc]) = rq;
+        }
+        __syncthreads();
+        if (j0 + 32 < je) fetch(j0 + 32);
+        const v8 afr = *reinterpret_cast<const v8 *>(&sP[buf][(16 * kb0 + c) * RS + 8 * g]);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) o[(16 * kb + 4 * g + i) * HP + 16 * lb + c] = acc[lb][i];
+        for (int i = 0; i < NBW; ++i) {
+            const v8 bfr = *reinterpret_cast<const v8 *>(&sQ[buf][(16 * (lb0 + i) + c) * RS + 8 * g]);
+            acc[i] = E::mfma(afr, bfr, acc[i]);
+        }
+        buf ^= 1;
     }
+    float *o = a.out + ((size_t)pair * gridDim.x + blockIdx.x) * HP * HP;
+#pragma unroll
+    for (int i = 0; i < NBW; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[(16 * kb0 + 4 * g + r) * HP + 16 * (lb0 + i) + c] = acc[i][r];
 }
 
 // Zero the columns [N, ldc) of an m x ldc coefficient buffer.
@@ -276,13 +304,16 @@ struct CombineArgs {
 };
 
 // dV[k][r] = -(rank-N product)[r][k] + sum_l y[r][l] M[l][k] (plus the lam
-// terms of the symmetric form).  256 threads: thread k = t % HP owns reflector
-// k for RT consecutive rows of its row group t / HP.  The y rows of the block
+// terms of the symmetric form).  256 threads for kCombineRows rows (two blocks
+// per compute unit at n = 8192): thread k = t % HP owns reflector k for RT
+// consecutive rows of its row group t / HP.  The y rows of the block
 // sit in LDS; the M matrices pass through LDS LC rows at a time, each element
 // serving RT rows.
+constexpr int kCombineRows = 16;
+
 template <int HP>
-__global__ __launch_bounds__(256) void k_wy_combine(CombineArgs a) {
-    constexpr int NG = 256 / HP, RT = 32 / NG, R = 32, LC = 8;
+__global__ __launch_bounds__(256, 2) void k_wy_combine(CombineArgs a) {
+    constexpr int NG = 256 / HP, R = kCombineRows, RT = R / NG, LC = 8;
     __shared__ double ys[R][HP + 1];
     __shared__ double sm[3][LC][HP];
     const int t = threadIdx.x;
@@ -297,18 +328,37 @@ __global__ __launch_bounds__(256) void k_wy_combine(CombineArgs a) {
     double yb[RT], ya[RT], yc[RT];
 #pragma unroll
     for (int i = 0; i < RT; ++i) yb[i] = ya[i] = yc[i] = 0.0;
+    // the next LC rows of the M matrices are fetched into registers while the
+    // current ones are used
+    constexpr int PER = LC * HP / 256;
+    double pre[3][PER];
+    auto fetch = [&](int l0) {
+#pragma unroll
+        for (int mi = 0; mi < 3; ++mi) {
+            if (mi < nm) {
+                const double *src = (mi == 0 ? a.Mb : mi == 1 ? a.Ma : a.Mc) + (size_t)l0 * HP;
+#pragma unroll
+                for (int q = 0; q < PER; ++q) pre[mi][q] = src[q * 256 + t];
+            }
+        }
+    };
+    fetch(0);
+#pragma unroll 1
     for (int l0 = 0; l0 < HP; l0 += LC) {
         __syncthreads();
-        for (int mi = 0; mi < nm; ++mi) {
-            const double *src = (mi == 0 ? a.Mb : mi == 1 ? a.Ma : a.Mc) + (size_t)l0 * HP;
 #pragma unroll
-            for (int q = 0; q < LC * HP / 256; ++q) {
-                const int e = q * 256 + t;
-                sm[mi][e / HP][e % HP] = src[e];
+        for (int mi = 0; mi < 3; ++mi) {
+            if (mi < nm) {
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    const int e = q * 256 + t;
+                    sm[mi][e / HP][e % HP] = pre[mi][q];
+                }
             }
         }
         __syncthreads();
-#pragma unroll
+        if (l0 + LC < HP) fetch(l0 + LC);
+#pragma unroll 2
         for (int ll = 0; ll < LC; ++ll) {
             const double mb = sm[0][ll][k];
             const double ma = sym ? sm[1][ll][k] : 0.0;
@@ -612,8 +662,8 @@ hh_status wy_backward16(hh_op op, const hh_desc *d, const void *U, int64_t ldu, 
     ca.h = (int)h;
     ca.npad = s.npad;
     ca.kind = kind;
-    if (hp == 64) hipLaunchKernelGGL(k_wy_combine<64>, dim3(s.npad / 32), dim3(256), 0, st, ca);
-    else hipLaunchKernelGGL(k_wy_combine<128>, dim3(s.npad / 32), dim3(256), 0, st, ca);
+    if (hp == 64) hipLaunchKernelGGL(k_wy_combine<64>, dim3(s.npad / kCombineRows), dim3(256), 0, st, ca);
+    else hipLaunchKernelGGL(k_wy_combine<128>, dim3(s.npad / kCombineRows), dim3(256), 0, st, ca);
     if (dU && h > 0)
         hipLaunchKernelGGL(k_wy_finish, dim3((unsigned)h), dim3(256), 0, st,
                            reinterpret_cast<const double *>(base + L.dv), s.npad, (int)n,
