@@ -52,8 +52,8 @@
  * Sizes (beyond them a call returns HH_ERR_UNSUPPORTED, nothing is enqueued):
  * FUSED forward n <= 8192 (F32) or 4096 (F64), any h (reflectors are staged
  * through on-chip memory in chunks); FUSED backward n <= 4096 (F32) or 2048
- * (F64), and all h reflectors together with the per-vector state must fit in
- * 64 KB of on-chip memory (roughly h * n * (4 or 8) bytes); WY n <= 8192,
+ * (F64), any h (the reflectors are staged in on-chip memory when they fit,
+ * else read through the caches); WY n <= 8192,
  * h <= 128, n and every leading dimension multiples of 8, 16-bit data 16-byte
  * aligned.
  *

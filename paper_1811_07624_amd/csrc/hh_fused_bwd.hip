@@ -14,12 +14,12 @@
 //
 // A wave owns V vectors (64 lanes x NC 16-byte chunks each) and walks their
 // chains side by side: the V dot products of a step are independent, which
-// hides the latency of their cross-lane reductions.  All h reflectors are
-// staged in LDS once per block (both sweeps walk them many times per vector);
-// shapes whose reflectors and per-vector state exceed the 64 KB LDS budget are
-// refused (HH_ERR_UNSUPPORTED; for FP32 h <= 29 at n = 512, h <= 13 at
-// n = 1024, h <= 1 at n = 4096, FP64 about half) and take the WY backward in
-// 16 bits.  dL/du for
+// hides the latency of their cross-lane reductions.  The h reflectors are
+// staged in LDS once per block when they fit with the per-vector state in the
+// 64 KB budget (both sweeps walk them many times per vector); otherwise both
+// sweeps read them from the workspace through the caches (UL = false).  A lane
+// holds at most 16 chunks of a vector, so n <= 4096 in FP32 and 2048 in FP64;
+// longer vectors are refused (HH_ERR_UNSUPPORTED).  dL/du for
 // HB reflectors at a time stays in registers across all the vectors a block
 // processes (shared by the V vectors of a wave); larger h takes several passes.  Each block writes its partial
 // sums; a second kernel adds the block partials in a fixed order in FP64
@@ -522,7 +522,8 @@ hipError_t launch_main(hh_op op, const FusedPlan &p, const FusedBwdArgs &a, dim3
     return hipGetLastError();
 }
 
-// ULO: only the form with the reflectors in LDS is instantiated.
+// ULO: only the form with the reflectors in LDS is instantiated (h <= 10,
+// whose reflectors always fit).
 template <typename T, int NC, int HB, bool ULO = false>
 hipError_t run_bwd_hb(hh_op op, const FusedPlan &p, const FusedBwdArgs &a, hipStream_t st) {
     constexpr int V = vpw_for<T, NC>();

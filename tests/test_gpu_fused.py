@@ -136,8 +136,10 @@ def test_qx_n64_h4_fp64_full():
 # ----------------------------------------------------------------------------
 # backward
 # ----------------------------------------------------------------------------
+# the last two have more reflector data than the on-chip budget (read through
+# the caches instead of staged in LDS)
 BSHAPES = [(64, 4, 300), (7, 3, 5), (100, 7, 129), (512, 9, 1000), (1024, 10, 77),
-           (300, 20, 50), (2048, 5, 20), (33, 0, 10), (16, 40, 9)]
+           (300, 20, 50), (2048, 5, 20), (33, 0, 10), (16, 40, 9), (1024, 40, 30), (2048, 24, 12)]
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -191,6 +193,35 @@ def test_mahal_bwd_parity(dtype, n, h, N):
     if h:
         assert rel_fro(host(dU), rU) < GTOL[dtype]
         assert rel_refl(host(dU), rU) < GTOL[dtype]
+
+
+@pytest.mark.parametrize("op", ["apply", "apply_T", "sym", "mahal"])
+def test_fused_bwd_fp32_n4096_h64(op):
+    """FP32 gradients at the headline shape (n = 4096, h = 64: 1 MiB of
+    reflectors, read through the caches) against the oracle, to the FP32
+    tolerances of the other backward tests."""
+    n, h, N, dtype = 4096, 64, 6, torch.float32
+    U, X = make(n, h, N, dtype, seed=5, unit=False)
+    G = torch.tensor(synth.gaussian((N, n), seed=6, stream=synth.STREAM_G), dtype=dtype, device=dev())
+    lam = torch.tensor(synth.eig_uniform(n, seed=7), dtype=dtype, device=dev())
+    if op in ("apply", "apply_T"):
+        dX, dU = P.apply_bwd_raw(U, X, G, trans=op == "apply_T")
+        torch.cuda.synchronize()
+        rdX, rdU = oracle.apply_bwd(host(U), host(X), host(G), trans=op == "apply_T")
+    elif op == "sym":
+        dX, dU, dlam = P.sym_bwd_raw(U, lam, X, G)
+        torch.cuda.synchronize()
+        rdX, rdU, rdlam = oracle.sym_bwd(host(U), host(lam), host(X), host(G))
+        assert rel_fro(host(dlam), rdlam) < GTOL[dtype]
+    else:
+        w = torch.tensor(synth.gaussian((N,), seed=8, stream=synth.STREAM_W), dtype=dtype, device=dev())
+        dX, _, dU, dlam = P.mahal_bwd_raw(U, lam, X, G, w)
+        torch.cuda.synchronize()
+        rdX, _, rdU, rdlam = oracle.mahal_bwd(host(U), host(lam), host(X), host(G), host(w))
+        assert rel_fro(host(dlam), rdlam) < GTOL[dtype]
+    assert rel_rows(host(dX), rdX) < TOL[dtype]
+    assert rel_fro(host(dU), rdU) < GTOL[dtype], rel_fro(host(dU), rdU)
+    assert rel_refl(host(dU), rdU) < GTOL[dtype], rel_refl(host(dU), rdU)
 
 
 def test_bwd_n_zero_writes_zero_grads():
