@@ -104,10 +104,12 @@ def algorithmic(op, n, h, N, io_bytes, param_bytes=4):
         nq = KNN_QUERIES
         npad = (n + 3) // 4 * 4
         return (N + nq) * n * io_bytes * 2, 2 * npad * nq * N + 4 * n * h * (N + nq)
-    if op == "mahal_fb":
-        fwd = (2 * n * io_bytes + param_bytes) * N
-        bwd = (2 * n * io_bytes + param_bytes) * N
-        return fwd + bwd, ((4 * h + 3) * n + 14 * n * h + 6 * n) * N
+    if op == "mahal_fb":  # the forward writes each pair's h dot products, the backward reads them
+        fwd = (2 * n * io_bytes + param_bytes + h * param_bytes) * N
+        bwd = (2 * n * io_bytes + param_bytes + h * param_bytes) * N
+        # backward: the chain again by its updates (2nh), then per reflector the
+        # rebuild, one dot product, the update and the two dU terms (10nh), and 6n
+        return fwd + bwd, ((4 * h + 3) * n + 12 * n * h + 6 * n) * N
     raise ValueError(op)
 
 
@@ -222,9 +224,9 @@ def main():
         elif op == "sym_fb":
             _, rec = P.sym_raw(U, lam, X, compute=tdt, out=Y, save=True)
             P.sym_bwd_raw(U, lam, X, Gd, compute=tdt, saved=rec)
-        else:
-            P.mahal_raw(U, lam, X, Xb)
-            P.mahal_bwd_raw(U, lam, X, Xb, w, need_dX=False)
+        else:  # the forward keeps each pair's dot products for the backward
+            _, rec = P.mahal_raw(U, lam, X, Xb, save=True)
+            P.mahal_bwd_raw(U, lam, X, Xb, w, need_dX=False, saved=rec)
 
     for _ in range(args.warmup):
         step()

@@ -235,6 +235,38 @@ HH_API hh_status hh_backward_saved(hh_op op, const hh_desc *d, const void *U, in
                             hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Record of the fused distance (FUSED algorithm only; not in the paper).  The
+ * backward of the distance d = sum_i lam_i ((Q^T (xa - xb))_i)^2 (Sec. IV-C)
+ * walks each pair's reflector chain forward again to rebuild s_h = Q^T (xa -
+ * xb), which takes the h dot products a_k = u_k^T s_{k-1} of Sec. II-A with
+ * their reductions.  hh_mahalanobis_save is hh_mahalanobis that also writes
+ * those dot products, as the forward formed them, into a caller-owned record;
+ * hh_mahalanobis_backward_saved reads them and rebuilds s_h by the updates
+ * alone.  Same results as the plain calls up to the rounding of the dot
+ * products (the forward's reduction order instead of the backward's).
+ *
+ * Record: N rows of the compute type, row j holding the h dot products of
+ * pair j (a_1 first) padded with zeros to a multiple of 16 bytes; device memory, at least hh_mahalanobis_saved_size bytes (HH_ERR_WORKSPACE
+ * if smaller); may be null when N == 0 or h == 0.  It stays valid for the same
+ * U, lam, Xa, Xb, n, h, N and dtypes; a record of other inputs gives wrong
+ * gradients, not an error.  The WY algorithm returns HH_ERR_UNSUPPORTED.
+ * Other arguments, validation and workspaces as for hh_mahalanobis and
+ * hh_mahalanobis_backward. */
+HH_API hh_status hh_mahalanobis_saved_size(const hh_desc *d, size_t *bytes);
+HH_API hh_status hh_mahalanobis_save(const hh_desc *d, const void *U, int64_t ldu,
+                                     const void *lam, const void *Xa, int64_t lda,
+                                     const void *Xb, int64_t ldb, void *dist, void *saved,
+                                     size_t saved_bytes, void *ws, size_t ws_bytes,
+                                     hipStream_t stream);
+HH_API hh_status hh_mahalanobis_backward_saved(const hh_desc *d, const void *U, int64_t ldu,
+                                               const void *lam, const void *Xa, int64_t lda,
+                                               const void *Xb, int64_t ldb, const void *saved,
+                                               size_t saved_bytes, const void *ddist, void *dXa,
+                                               void *dXb, int64_t lddx, void *dU, int64_t lddu,
+                                               void *dlam, void *ws, size_t ws_bytes,
+                                               hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Diagonal D on either side (Sec. II-A, eq. 1: the factorisation is D times
  * the reflector product, with D = diag(d), d in {+1, -1}^n; Result 3 puts D
  * on the right of the product instead; Sec. III-A, eq. thesbar: D on both

@@ -26,6 +26,7 @@ EXPORTS = (
     "hh_mahalanobis_backward", "hh_saved_size", "hh_forward_save", "hh_backward_saved",
     "hh_forward_signed", "hh_backward_signed", "hh_forward_noalloc", "hh_factor_workspace_size",
     "hh_factor_orthonormal", "hh_shf_workspace_size", "hh_shf", "hh_knn_workspace_size", "hh_knn",
+    "hh_mahalanobis_saved_size", "hh_mahalanobis_save", "hh_mahalanobis_backward_saved",
     "hh_status_string",
     "hh_last_error", "hh_version",
 )
@@ -88,6 +89,9 @@ def lib():
         "hh_shf": [I, I, I, ctypes.c_int, P, I, P, I, P, P, P, P, S, P],
         "hh_knn_workspace_size": [I, I, I, I, ctypes.POINTER(S)],
         "hh_knn": [I, I, I, I, P, I, P, I, P, P, P, S, P],
+        "hh_mahalanobis_saved_size": [D, ctypes.POINTER(S)],
+        "hh_mahalanobis_save": [D, P, I, P, P, I, P, I, P, P, S, P, S, P],
+        "hh_mahalanobis_backward_saved": [D, P, I, P, P, I, P, I, P, S, P, P, P, I, P, I, P, P, S, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -126,7 +130,10 @@ def ptr(t):
 
 
 def ld(t: torch.Tensor) -> int:
-    """Leading dimension of an (rows, n) tensor whose rows are contiguous."""
+    """Leading dimension of an (rows, n) tensor whose rows are contiguous (an
+    empty tensor's strides mean nothing: its leading dimension is n)."""
+    if t.dim() == 2 and t.numel() == 0:
+        return max(int(t.shape[1]), 1)
     if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
         raise ValueError("expected a 2-D tensor with unit stride along its last dimension")
     return max(int(t.stride(0)), int(t.shape[1]))

@@ -177,6 +177,14 @@ static hh_status make_fused_bwd_plan(const hh_desc *d, FusedPlan *p) {
 
 static int aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
+// Record of the fused distance: the h dot products of every pair, one row of
+// h rounded up to 16 bytes per pair, in the compute type.
+static size_t mahal_dots_bytes(const hh_desc *d) {
+    const size_t es = dtype_size(d->compute_dtype), rw = 16 / es;
+    const size_t hp = ((size_t)d->h + rw - 1) / rw * rw;
+    return align256(hp * (size_t)d->N * es);
+}
+
 // ---------------------------------------------------------------------------
 // Forward entry (all four ops).
 static hh_status forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
@@ -198,11 +206,14 @@ static hh_status forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
         return wy_forward(op, d, U, ldu, lam, X, ldx, Xb, ldb, Y, ldy, saved, saved_bytes, ws,
                           ws_bytes, st);
     }
-    if (saved) return fail(HH_ERR_UNSUPPORTED, "a coefficient record exists on the WY path only");
+    if (saved && op != HH_OP_MAHAL)
+        return fail(HH_ERR_UNSUPPORTED, "a coefficient record exists on the WY path only");
 
     FusedPlan p;
     HH_TRY(make_fused_plan(d, &p, (din ? 1 : 0) + (dout ? 1 : 0)));
     const FusedWs w = fused_ws(op, p);
+    if (saved && saved_bytes < mahal_dots_bytes(d))
+        return fail(HH_ERR_WORKSPACE, "record needs %zu bytes, got %zu", mahal_dots_bytes(d), saved_bytes);
     if (N == 0) return HH_OK;
     if (h > 0) HH_TRY(check_ptr("U", U));
     HH_TRY(check_ptr(op == HH_OP_MAHAL ? "Xa" : "X", X));
@@ -247,6 +258,7 @@ static hh_status forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
     else vec = vec && aligned16(Y) && (ldy % wvec == 0);
     a.vec_ok = vec ? 1 : 0;
     a.skip_zeros = d->algo == HH_ALGO_FUSED_QR ? 1 : 0;
+    a.dots = saved;
     FusedOp fop = op == HH_OP_APPLY ? F_APPLY : op == HH_OP_APPLY_T ? F_APPLY_T
                 : op == HH_OP_SYM ? F_SYM : F_MAHAL;
     e = launch_fused_fwd(p, fop, a, st);
@@ -279,14 +291,17 @@ static hh_status backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu
     if (algo == Algo::WY)
         return wy_backward(op, d, U, ldu, lam, X, ldx, Xb, ldb, G, ldg, dX, dXb, lddx, dU, lddu,
                            dlam, saved, saved_bytes, ws, ws_bytes, st);
-    if (saved) return fail(HH_ERR_UNSUPPORTED, "a coefficient record exists on the WY path only");
+    if (saved && op != HH_OP_MAHAL_BWD)
+        return fail(HH_ERR_UNSUPPORTED, "a coefficient record exists on the WY path only");
 
     FusedPlan p;
     HH_TRY(make_fused_bwd_plan(d, &p));
     if (!fused_bwd_supported(op, p))
         return fail(HH_ERR_UNSUPPORTED,
-                    "fused backward needs all h reflectors in LDS (n = %lld, h = %lld)",
+                    "fused backward's per-vector state does not fit in on-chip memory (n = %lld, h = %lld)",
                     (long long)n, (long long)h);
+    if (saved && saved_bytes < mahal_dots_bytes(d))
+        return fail(HH_ERR_WORKSPACE, "record needs %zu bytes, got %zu", mahal_dots_bytes(d), saved_bytes);
     const FusedWs w = fused_ws(op, p);
     if (h > 0) HH_TRY(check_ptr("U", U));
     if (N > 0) {
@@ -329,6 +344,7 @@ static hh_status backward(hh_op op, const hh_desc *d, const void *U, int64_t ldu
     a.scratch = base + w.bwd;
     a.din = din;
     a.dout = dout;
+    a.dots = saved;
     a.n = (int)n;
     a.h = (int)h;
     a.npad = p.s.npad;
@@ -552,6 +568,44 @@ hh_status hh_backward_saved(hh_op op, const hh_desc *d, const void *U, int64_t l
                     lddx, dU, lddu, sym ? dlam : nullptr, ws, ws_bytes, stream, saved, saved_bytes);
 }
 
+hh_status hh_mahalanobis_saved_size(const hh_desc *d, size_t *bytes) {
+    if (!bytes) return fail(HH_ERR_INVALID_ARG, "bytes must not be null");
+    Algo algo;
+    HH_TRY(check_desc(d, &algo));
+    if (algo == Algo::WY) return fail(HH_ERR_UNSUPPORTED, "the distance record exists on the fused path only");
+    FusedPlan p;
+    HH_TRY(make_fused_plan(d, &p));
+    *bytes = mahal_dots_bytes(d);
+    return HH_OK;
+}
+
+hh_status hh_mahalanobis_save(const hh_desc *d, const void *U, int64_t ldu, const void *lam,
+                              const void *Xa, int64_t lda, const void *Xb, int64_t ldb, void *dist,
+                              void *saved, size_t saved_bytes, void *ws, size_t ws_bytes,
+                              hipStream_t stream) {
+    Algo algo;
+    HH_TRY(check_desc(d, &algo));
+    if (algo == Algo::WY) return fail(HH_ERR_UNSUPPORTED, "the distance record exists on the fused path only");
+    if (d->N > 0 && d->h > 0) HH_TRY(check_ptr("saved", saved));
+    return forward(HH_OP_MAHAL, d, U, ldu, lam, Xa, lda, Xb, ldb, dist, 0, ws, ws_bytes, stream,
+                   d->N > 0 && d->h > 0 ? saved : nullptr, saved_bytes);
+}
+
+hh_status hh_mahalanobis_backward_saved(const hh_desc *d, const void *U, int64_t ldu,
+                                        const void *lam, const void *Xa, int64_t lda,
+                                        const void *Xb, int64_t ldb, const void *saved,
+                                        size_t saved_bytes, const void *ddist, void *dXa,
+                                        void *dXb, int64_t lddx, void *dU, int64_t lddu,
+                                        void *dlam, void *ws, size_t ws_bytes, hipStream_t stream) {
+    Algo algo;
+    HH_TRY(check_desc(d, &algo));
+    if (algo == Algo::WY) return fail(HH_ERR_UNSUPPORTED, "the distance record exists on the fused path only");
+    if (d->N > 0 && d->h > 0) HH_TRY(check_ptr("saved", saved));
+    return backward(HH_OP_MAHAL_BWD, d, U, ldu, lam, Xa, lda, Xb, ldb, ddist, 0, dXa, dXb, lddx, dU,
+                    lddu, dlam, ws, ws_bytes, stream, d->N > 0 && d->h > 0 ? saved : nullptr,
+                    saved_bytes);
+}
+
 const char *hh_status_string(hh_status s) {
     switch (s) {
     case HH_OK: return "HH_OK";
@@ -565,6 +619,6 @@ const char *hh_status_string(hh_status s) {
 
 const char *hh_last_error(void) { return g_last_error.c_str(); }
 
-int hh_version(void) { return 400; }  // 0.4.0: allocation-free forward (hh_forward_noalloc)
+int hh_version(void) { return 410; }  // 0.4.1: distance record (hh_mahalanobis_save)
 
 }  // extern "C"

@@ -23,6 +23,7 @@ struct FusedBwdArgs {
     void *scratch;    // per-block partial sums
     const void *din;  // n diagonal entries on the forward's input, or null
     const void *dout; // n diagonal entries on the forward's output, or null
+    const void *dots; // Mahalanobis, nullable: the forward's dot products, rows of h padded to 16 bytes
     int n, h, npad;
     int64_t N;
     int vec_ok;

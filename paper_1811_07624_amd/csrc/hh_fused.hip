@@ -17,7 +17,9 @@
 // A reflector whose first nonzero entry lies past whole chunks (reflectors of
 // a Householder QR have k - 1 leading zeros, the remark after Result 3) skips
 // those chunks in its dot product and update: 4(n - k + 1) operations instead
-// of 4n, with the same result (the skipped terms are exact zeros).
+// of 4n, with the same result (the skipped terms are exact zeros).  The
+// distance kernel can also write each pair's h dot products (a record the
+// backward reads instead of forming them again).
 #include <algorithm>
 #include <type_traits>
 
@@ -112,6 +114,40 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
         loaded = q;
     };
     if (nchunks == 1) load_chunk(0);
+    // Record of the distance's dot products: row j (hp = h rounded up to 16
+    // bytes, the padding zero) holds pair j's.  Each wave stages its vectors'
+    // dot products of the current reflector chunk in LDS (rows of hcp values),
+    // then writes them with consecutive lanes: whole padded rows at once when
+    // one chunk holds all h reflectors, so that the rows of a batch step cover
+    // whole cache lines (partial-line writes are costly).
+    constexpr int RW = 16 / (int)sizeof(T);
+    const int hp = (h + RW - 1) / RW * RW, hcp = (hc + RW - 1) / RW * RW;
+    constexpr int NVW = VPW * VPL;  // vectors of a wave
+    T *sDots = reinterpret_cast<T *>(reinterpret_cast<uintptr_t>(sLead + hc + 3) & ~(uintptr_t)15);
+    if constexpr (OP == F_MAHAL)
+        if (a.dots)  // the padding slots stay zero
+            for (int i = lane; i < NVW * hcp; i += kWave) sDots[wave * NVW * hcp + i] = (T)0;
+    int64_t jwave = 0;  // first vector of the wave in the current batch step
+    // rows jw .. jw + NVW - 1, reflectors kb .. ke - 1 of the record
+    auto flush_dots = [&](int64_t jw, int kb, int ke) {
+        const int cnt = ke - kb;
+        T *dst = static_cast<T *>(a.dots);
+        if (cnt == h && jw + NVW <= a.N) {  // whole padded rows: a straight copy
+            for (int l = lane; l < NVW * hp; l += kWave) dst[jw * hp + l] = sDots[wave * NVW * hp + l];
+            return;
+        }
+        const int wid = ke == h ? hp - kb : cnt;  // the last chunk also writes the row's padding
+        for (int l = lane; l < NVW * wid; l += kWave) {
+            const int vi = l / wid, kk = l % wid;
+            const int64_t j = jw + vi;
+            if (j < a.N) dst[j * hp + kb + kk] = kk < cnt ? sDots[(wave * NVW + vi) * hcp + kk] : (T)0;
+        }
+    };
+    // With all h reflectors in one chunk, a batch step's dot products wait in
+    // LDS and are written after the next step's loads are issued (vector-memory
+    // counters retire in issue order: stores issued before those loads would
+    // hold up the wait for them); else each chunk's are written at once.
+    int64_t jprev = -1;
 
     // One reflection of the lane's slices of its VPL vectors by reflector k,
     // over chunks S .. NC-1 (S = 0: the whole vector).
@@ -135,6 +171,8 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
 #pragma unroll
             for (int q = 1; q < W; ++q) p += part[q];
             p = group_sum<LPV>(p);
+            if constexpr (OP == F_MAHAL)
+                if (a.dots && c == 0) sDots[((wave * VPW + row) * VPL + v) * hcp + (k - loaded * hc)] = p;
             const T coef = -p * tk;
 #pragma unroll
             for (int i = S; i < NC; ++i)
@@ -179,6 +217,8 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
             load_chunk(q);
             const int kend = min(h, (q + 1) * hc);
             run_chunk(q * hc, kend, 1, x);
+            if constexpr (OP == F_MAHAL)
+                if (a.dots && nchunks > 1) flush_dots(jwave, q * hc, kend);
         }
     };
     auto run_down = [&](T(&x)[VPL][E]) {  // k = h-1 .. 0  (Q: H_h first)
@@ -238,15 +278,18 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
     const int64_t joff = (int64_t)(wave * VPW + row) * VPL;
     for (int64_t b0 = (int64_t)blockIdx.x * vpb; b0 < a.N; b0 += gstride) {
         const int64_t j0 = b0 + joff;
+        jwave = b0 + (int64_t)wave * VPW * VPL;
         T x[VPL][E];
 #pragma unroll
         for (int v = 0; v < VPL; ++v) load_vec(x[v], static_cast<const T *>(a.X), a.ldx, j0 + v, j0 + v < a.N);
         if constexpr (OP == F_MAHAL && VPL == 1) {
             T xb[E];
             load_vec(xb, static_cast<const T *>(a.Xb), a.ldb, j0, j0 < a.N);
+            if (a.dots && nchunks == 1 && jprev >= 0) flush_dots(jprev, 0, h);  // behind this step's loads
 #pragma unroll
             for (int e = 0; e < E; ++e) x[0][e] -= xb[e];
         } else if constexpr (OP == F_MAHAL) {
+            if (a.dots && nchunks == 1 && jprev >= 0) flush_dots(jprev, 0, h);
             // x - xb one 16-byte chunk at a time (keeps the second input's
             // registers to one chunk when a lane holds two vectors)
             const T *Xb = static_cast<const T *>(a.Xb);
@@ -273,6 +316,8 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
         if (a.din) scale(x, sDin);
         if constexpr (OP == F_APPLY) run_down(x);
         if constexpr (OP == F_APPLY_T || OP == F_SYM || OP == F_MAHAL) run_up(x);
+        if constexpr (OP == F_MAHAL)
+            if (a.dots && nchunks == 1) jprev = jwave;
         if constexpr (OP == F_SYM) {
 #pragma unroll
             for (int i = 0; i < NC; ++i) {
@@ -305,6 +350,8 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
             }
         }
     }
+    if constexpr (OP == F_MAHAL)
+        if (a.dots && nchunks == 1 && jprev >= 0) flush_dots(jprev, 0, h);
 }
 
 template <typename T, int LPV, int NC, int VPL, int WPB, bool SKIP>
@@ -321,9 +368,15 @@ hipError_t launch_op_s(FusedOp op, const FusedPlan &p, const FusedFwdArgs &a, di
     case F_SYM:
         hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_SYM, VPL, WPB, SKIP>), grid, block, p.lds_bytes, st, a);
         break;
-    case F_MAHAL:
-        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_MAHAL, VPL, WPB, SKIP>), grid, block, p.lds_bytes, st, a);
+    case F_MAHAL: {
+        // the dot-product staging of the record: hc values per vector of the block, 16-byte aligned
+        constexpr size_t es = sizeof(T);
+        const size_t rw = 16 / es, hcp = (p.hc + rw - 1) / rw * rw;
+        const size_t stage = a.dots ? 16 + (size_t)WPB * (kWave / LPV) * VPL * hcp * es : 0;
+        hipLaunchKernelGGL((k_fused_fwd<T, LPV, NC, F_MAHAL, VPL, WPB, SKIP>), grid, block, p.lds_bytes + stage, st,
+                           a);
         break;
+    }
     }
     return hipGetLastError();
 }

@@ -8,7 +8,9 @@
 //     dL/ds_{r-1} = g_r - tau (u^T g_r) u          (H is symmetric)
 //     dL/du      += -tau [ (u^T s_{r-1}) g_r + (u^T g_r) s_{r-1} ]
 // Intermediate vectors are not stored: the forward sweep keeps only the h dot
-// products a_r = u^T s_{r-1} (in LDS), and the reverse sweep rebuilds
+// products a_r = u^T s_{r-1} (in LDS; for the distance, a record the forward
+// wrote can supply them, and the forward sweep is then updates only), and the
+// reverse sweep rebuilds
 // s_{r-1} = s_r + tau a_r u, which undoes the forward update exactly up to one
 // rounding because H is its own inverse.
 //
@@ -349,7 +351,27 @@ __global__ __launch_bounds__(kThreads) void k_fused_bwd(FusedBwdArgs a, int k0, 
             }
             rev_chain(true, s, g, 0);
         } else {  // B_MAHAL
-            fwd_chain(true, s, 0);
+            if (a.dots) {
+                // the forward's dot products into the wave's slots, then the
+                // forward sweep without dot products or reductions
+                const T *dp = static_cast<const T *>(a.dots);
+                constexpr int RW = 16 / (int)sizeof(T);
+                const int hp = (h + RW - 1) / RW * RW;  // record row length
+                for (int l = lane; l < V * h; l += kWave) {
+                    const int v = l / h, r = l % h;
+                    myAl[v * RS + r] = (j0 + v < a.N) ? dp[(j0 + v) * hp + r] : (T)0;
+                }
+#pragma unroll 1
+                for (int r = 0; r < h; ++r) {
+                    VT uv[NC];
+                    load_u(r, uv);
+                    const T t = sTau[r];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) axpy(-myAl[v * RS + r] * t, uv, s[v]);
+                }
+            } else {
+                fwd_chain(true, s, 0);
+            }
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const T w = (j0 + v < a.N) ? static_cast<const T *>(a.G)[j0 + v] : (T)0;

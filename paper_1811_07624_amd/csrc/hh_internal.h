@@ -177,6 +177,7 @@ struct FusedFwdArgs {
     int64_t N;
     int vec_ok;  // 16-byte accesses are legal for every data operand
     int skip_zeros;  // run the kernels that skip each reflector's leading zero chunks
+    void *dots;      // MAHAL, nullable: the h dot products u_k^T s_{k-1} of each pair, rows of h padded to 16 bytes
 };
 
 hipError_t launch_fused_fwd(const FusedPlan &p, FusedOp op, const FusedFwdArgs &a,

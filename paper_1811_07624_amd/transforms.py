@@ -122,7 +122,11 @@ def sym_raw(U, lam, X, compute=None, algo="auto", out=None, save=False):
     return Y
 
 
-def mahal_raw(U, lam, Xa, Xb, compute=None, algo="auto"):
+def mahal_raw(U, lam, Xa, Xb, compute=None, algo="auto", save=False):
+    """Distances d_j = sum_i lam_i ((Q^T (xa_j - xb_j))_i)^2.  save=True (fused
+    algorithm) returns (d, record): the record holds each pair's h dot
+    products, which mahal_bwd_raw(..., saved=record) reads instead of forming
+    them again."""
     _check_dev(U, lam, Xa, Xb)
     Xa, Xb = _rows(Xa), _rows(Xb)
     param, io, comp = _cfg(Xa, compute)
@@ -132,10 +136,20 @@ def mahal_raw(U, lam, Xa, Xb, compute=None, algo="auto"):
     desc = L.make_desc(n, h, N, param, io, comp, algo)
     d = torch.empty((N,), dtype=param, device=Xa.device)
     ws = L.workspace(L.HH_OP_MAHAL, desc, Xa.device)
-    L.check("hh_mahalanobis", L.lib().hh_mahalanobis(
-        ctypes.byref(desc), L.ptr(U), max(n, U.stride(0) if h else n), L.ptr(lam), L.ptr(Xa),
-        L.ld(Xa), L.ptr(Xb), L.ld(Xb), L.ptr(d), L.ptr(ws), ws.numel(), L.stream_of(Xa)))
-    return d
+    ldu = max(n, U.stride(0) if h else n)
+    if not save:
+        L.check("hh_mahalanobis", L.lib().hh_mahalanobis(
+            ctypes.byref(desc), L.ptr(U), ldu, L.ptr(lam), L.ptr(Xa), L.ld(Xa), L.ptr(Xb), L.ld(Xb),
+            L.ptr(d), L.ptr(ws), ws.numel(), L.stream_of(Xa)))
+        return d
+    nb = ctypes.c_size_t(0)
+    L.check("hh_mahalanobis_saved_size", L.lib().hh_mahalanobis_saved_size(ctypes.byref(desc),
+                                                                             ctypes.byref(nb)))
+    rec = torch.empty((max(nb.value, 1),), dtype=torch.uint8, device=Xa.device)
+    L.check("hh_mahalanobis_save", L.lib().hh_mahalanobis_save(
+        ctypes.byref(desc), L.ptr(U), ldu, L.ptr(lam), L.ptr(Xa), L.ld(Xa), L.ptr(Xb), L.ld(Xb),
+        L.ptr(d), L.ptr(rec), nb.value, L.ptr(ws), ws.numel(), L.stream_of(Xa)))
+    return d, rec
 
 
 def signed_raw(op, U, X, d_in=None, d_out=None, lam=None, Xb=None, compute=None, algo="auto",
@@ -265,7 +279,9 @@ def sym_bwd_raw(U, lam, X, dY, compute=None, algo="auto", need_dX=True, need_dU=
 
 
 def mahal_bwd_raw(U, lam, Xa, Xb, dd, compute=None, algo="auto", need_dX=True, need_dU=True,
-                  need_dlam=True):
+                  need_dlam=True, saved=None):
+    """Gradients (dXa, dXb, dU, dlam) of sum_j dd_j d_j.  saved: the record of
+    mahal_raw(..., save=True) on the same inputs."""
     _check_dev(U, lam, Xa, Xb, dd)
     Xa, Xb = _rows(Xa), _rows(Xb)
     param, io, comp = _cfg(Xa, compute)
@@ -278,10 +294,18 @@ def mahal_bwd_raw(U, lam, Xa, Xb, dd, compute=None, algo="auto", need_dX=True, n
     dU = torch.empty((h, n), dtype=param, device=Xa.device) if need_dU else None
     dlam = torch.empty((n,), dtype=param, device=Xa.device) if need_dlam else None
     ws = L.workspace(L.HH_OP_MAHAL_BWD, desc, Xa.device)
-    L.check("hh_mahalanobis_backward", L.lib().hh_mahalanobis_backward(
-        ctypes.byref(desc), L.ptr(U), max(n, U.stride(0) if h else n), L.ptr(lam), L.ptr(Xa),
-        L.ld(Xa), L.ptr(Xb), L.ld(Xb), L.ptr(dd), L.ptr(dXa), L.ptr(dXb), n, L.ptr(dU), n,
-        L.ptr(dlam), L.ptr(ws), ws.numel(), L.stream_of(Xa)))
+    ldu = max(n, U.stride(0) if h else n)
+    if saved is None:
+        L.check("hh_mahalanobis_backward", L.lib().hh_mahalanobis_backward(
+            ctypes.byref(desc), L.ptr(U), ldu, L.ptr(lam), L.ptr(Xa), L.ld(Xa), L.ptr(Xb), L.ld(Xb),
+            L.ptr(dd), L.ptr(dXa), L.ptr(dXb), n, L.ptr(dU), n, L.ptr(dlam), L.ptr(ws), ws.numel(),
+            L.stream_of(Xa)))
+    else:
+        _check_dev(saved)
+        L.check("hh_mahalanobis_backward_saved", L.lib().hh_mahalanobis_backward_saved(
+            ctypes.byref(desc), L.ptr(U), ldu, L.ptr(lam), L.ptr(Xa), L.ld(Xa), L.ptr(Xb), L.ld(Xb),
+            L.ptr(saved), saved.numel(), L.ptr(dd), L.ptr(dXa), L.ptr(dXb), n, L.ptr(dU), n,
+            L.ptr(dlam), L.ptr(ws), ws.numel(), L.stream_of(Xa)))
     return dXa, dXb, dU, dlam
 
 
@@ -389,6 +413,13 @@ class _Mahal(torch.autograd.Function):
     def forward(ctx, U, lam, Xa, Xb, compute, algo):
         ctx.cfg = (compute, algo)
         ctx.save_for_backward(U, lam, Xa, Xb)
+        ctx.rec = None
+        comp = _cfg(Xa, compute)[2]
+        fused = algo in ("auto", "fused", "fused_qr") and comp in (torch.float32, torch.float64)
+        if fused and (ctx.needs_input_grad[0] or ctx.needs_input_grad[1]):
+            # the forward keeps its dot products for the backward (h values per pair)
+            d, ctx.rec = mahal_raw(U, lam, Xa, Xb, compute, algo, save=True)
+            return d
         return mahal_raw(U, lam, Xa, Xb, compute, algo)
 
     @staticmethod
@@ -398,7 +429,8 @@ class _Mahal(torch.autograd.Function):
         need_x = ctx.needs_input_grad[2] or ctx.needs_input_grad[3]
         dXa, dXb, dU, dlam = mahal_bwd_raw(U, lam, Xa, Xb, dd.contiguous(), compute, algo,
                                            need_dX=need_x, need_dU=ctx.needs_input_grad[0],
-                                           need_dlam=ctx.needs_input_grad[1])
+                                           need_dlam=ctx.needs_input_grad[1], saved=ctx.rec)
+        ctx.rec = None
         if dU is not None:
             dU = dU.to(U.dtype)
         if dlam is not None:

@@ -320,3 +320,36 @@ def test_knn_validation():
     assert call(ldq=7) == L.HH_ERR_INVALID_ARG
     assert call(ptr=0) == L.HH_ERR_INVALID_ARG
     assert call(Nq=0, ptr=0) == L.HH_OK
+
+
+def test_mahal_record_validation():
+    """The distance record (fused path): its size, and the checks that fail
+    before anything is enqueued (fake pointers: nothing is dereferenced)."""
+    v = ctypes.c_void_p
+    lib = P.lib()
+    nb = ctypes.c_size_t(0)
+    d = _desc(n=8, h=3, N=100)
+    assert lib.hh_mahalanobis_saved_size(ctypes.byref(d), ctypes.byref(nb)) == L.HH_OK
+    assert nb.value == -(-4 * 100 * 4 // 256) * 256  # N rows of h = 3 padded to 4 FP32 values
+    d64 = _desc(n=8, h=3, N=100, p=L.HH_F64, io=L.HH_F64, c=L.HH_F64)
+    assert lib.hh_mahalanobis_saved_size(ctypes.byref(d64), ctypes.byref(nb)) == L.HH_OK
+    assert nb.value == -(-4 * 100 * 8 // 256) * 256  # rows of 3 FP64 values padded to 4
+    assert lib.hh_mahalanobis_saved_size(ctypes.byref(d), None) == L.HH_ERR_INVALID_ARG
+    assert lib.hh_mahalanobis_saved_size(ctypes.byref(_wy_desc()), ctypes.byref(nb)) == L.HH_ERR_UNSUPPORTED
+    lib.hh_mahalanobis_saved_size(ctypes.byref(d), ctypes.byref(nb))
+
+    def fwd(saved=4096, sb=nb.value, desc=d):
+        return lib.hh_mahalanobis_save(ctypes.byref(desc), v(1024), 8, v(2048), v(3072), 8, v(5120), 8,
+                                       v(6144), v(saved) if saved else None, sb, v(8192), 1 << 40, None)
+    assert fwd(saved=0) == L.HH_ERR_INVALID_ARG
+    assert fwd(sb=nb.value - 1) == L.HH_ERR_WORKSPACE
+    assert fwd(desc=_wy_desc()) == L.HH_ERR_UNSUPPORTED
+
+    def bwd(saved=4096, sb=nb.value, desc=d):
+        return lib.hh_mahalanobis_backward_saved(ctypes.byref(desc), v(1024), 8, v(2048), v(3072), 8,
+                                                 v(5120), 8, v(saved) if saved else None, sb, v(6144),
+                                                 v(7168), v(9216), 8, v(10240), 8, v(11264), v(12288),
+                                                 1 << 40, None)
+    assert bwd(saved=0) == L.HH_ERR_INVALID_ARG
+    assert bwd(sb=nb.value - 1) == L.HH_ERR_WORKSPACE
+    assert bwd(desc=_wy_desc()) == L.HH_ERR_UNSUPPORTED

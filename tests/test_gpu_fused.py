@@ -224,6 +224,59 @@ def test_fused_bwd_fp32_n4096_h64(op):
     assert rel_refl(host(dU), rdU) < GTOL[dtype], rel_refl(host(dU), rdU)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n,h,N", [(512, 9, 1000), (100, 7, 129), (1024, 40, 30), (33, 0, 10),
+                                   (7, 3, 5), (64, 4, 0)])
+def test_mahal_bwd_from_record(dtype, n, h, N):
+    """Distances with the record of dot products (hh_mahalanobis_save) equal the
+    plain ones exactly, and the backward from the record meets the oracle to the
+    stated tolerances; it differs from the plain backward only by the rounding
+    of the dot products (the forward's reduction order)."""
+    U, Xa = make(n, h, N, dtype, seed=17 * n + h)
+    Xb = torch.tensor(synth.gaussian((N, n), seed=3, stream=synth.STREAM_XB), dtype=dtype, device=dev())
+    lam = torch.tensor(synth.eig_uniform(n, seed=n), dtype=dtype, device=dev())
+    w = torch.tensor(synth.gaussian((N,), seed=4, stream=synth.STREAM_W), dtype=dtype, device=dev())
+    d0 = P.mahal_raw(U, lam, Xa, Xb)
+    d1, rec = P.mahal_raw(U, lam, Xa, Xb, save=True)
+    g0 = P.mahal_bwd_raw(U, lam, Xa, Xb, w)
+    g1 = P.mahal_bwd_raw(U, lam, Xa, Xb, w, saved=rec)
+    torch.cuda.synchronize()
+    assert torch.equal(d0, d1)
+    if N == 0:
+        return
+    rXa, rXb, rU, rlam = oracle.mahal_bwd(host(U), host(lam), host(Xa), host(Xb), host(w))
+    dXa, dXb, dU, dlam = g1
+    assert rel_rows(host(dXa), rXa) < TOL[dtype]
+    assert torch.equal(dXb, -dXa)
+    assert rel_fro(host(dlam), rlam) < GTOL[dtype]
+    if h:
+        assert rel_fro(host(dU), rU) < GTOL[dtype]
+        assert rel_refl(host(dU), rU) < GTOL[dtype]
+        # the record holds the forward's dot products u_k^T s_{k-1}, pair j in row j
+        es = 8 if dtype == torch.float64 else 4
+        hp = -(-h * es // 16) * 16 // es  # rows padded to 16 bytes
+        rows = rec[: hp * N * es].view(dtype).view(N, hp)
+        assert not rows[:, h:].any()
+        dots = rows[:, :h].T
+        ref = oracle_dots(host(U), host(Xa) - host(Xb))
+        assert np.abs(host(dots) - ref).max() <= TOL[dtype] * np.abs(ref).max()
+    for a, b in zip(g0, g1):
+        assert rel_fro(host(a), host(b)) < GTOL[dtype]
+
+
+def oracle_dots(U, V):
+    """u_k^T s_{k-1} along the chain s_k = H_k s_{k-1} that Q^T v applies
+    (unit u_k = U_k / ||U_k||), one row per reflector, by the definition."""
+    h = U.shape[0]
+    S = V.T.copy()
+    out = np.zeros((h, V.shape[0]))
+    for k in range(h):
+        u = U[k] / np.linalg.norm(U[k])
+        out[k] = u @ S
+        S -= 2.0 * np.outer(u, out[k])
+    return out
+
+
 def test_bwd_n_zero_writes_zero_grads():
     U, _ = make(40, 3, 1, torch.float32)
     E = torch.empty((0, 40), dtype=torch.float32, device=dev())
