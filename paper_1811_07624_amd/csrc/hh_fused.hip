@@ -123,7 +123,10 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
     constexpr int RW = 16 / (int)sizeof(T);
     const int hp = (h + RW - 1) / RW * RW, hcp = (hc + RW - 1) / RW * RW;
     constexpr int NVW = VPW * VPL;  // vectors of a wave
-    T *sDots = reinterpret_cast<T *>(reinterpret_cast<uintptr_t>(sLead + hc + 3) & ~(uintptr_t)15);
+    // (an offset from smem, 16-byte aligned: arithmetic on the LDS base keeps
+    // the accesses ds_read / ds_write instead of generic flat ones)
+    const int dots_off = ((int)(reinterpret_cast<unsigned char *>(sLead + hc) - smem) + 15) & ~15;
+    T *sDots = reinterpret_cast<T *>(smem + dots_off);
     if constexpr (OP == F_MAHAL)
         if (a.dots)  // the padding slots stay zero
             for (int i = lane; i < NVW * hcp; i += kWave) sDots[wave * NVW * hcp + i] = (T)0;
