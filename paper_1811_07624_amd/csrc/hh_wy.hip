@@ -47,11 +47,13 @@ constexpr int kThreadsWY = kWaves * kWave;
 
 // ---------------------------------------------------------------------------
 // Setup kernels (FP64).
-// One block of kNormThreads per reflector k: u_k / ||u_k|| in FP64, rounded to
-// the 16-bit type and written to the three fragment-ordered copies, with
-// ||y_k||^2 of the rounded vector.  Sums: wave shuffles, then the wave
-// partials in a fixed order.
-constexpr int kNormThreads = 256;
+// One block of kNormThreads per reflector k, u_k held in registers (n <=
+// npad <= kNormThreads * kNormPer = 8192, the compact-WY limit; all loads of
+// a thread issued together): u_k / ||u_k|| in FP64, rounded to the 16-bit
+// type and written to the three fragment-ordered copies, with ||y_k||^2 of
+// the rounded vector.  Sums: wave shuffles, then the wave partials in a
+// fixed order.
+constexpr int kNormThreads = 1024, kNormPer = 8;
 
 __device__ __forceinline__ double wave_sum_f64(double v) {
 #pragma unroll
@@ -84,45 +86,61 @@ __global__ __launch_bounds__(kNormThreads) void k_wy_norm(const float *__restric
     __shared__ double red[kNormThreads / kWave];
     const int k = blockIdx.x;
     const int t = threadIdx.x;
+    const bool live = k < h;
+    float u[kNormPer];
+#pragma unroll
+    for (int m = 0; m < kNormPer; ++m) {
+        const int i = t + kNormThreads * m;
+        u[m] = (live && i < n) ? U[(int64_t)k * ldu + i] : 0.f;
+    }
     double s = 0.0;
-    if (k < h)
-        for (int i = t; i < n; i += kNormThreads) {
-            const double v = (double)U[(int64_t)k * ldu + i];
-            s += v * v;
-        }
+#pragma unroll
+    for (int m = 0; m < kNormPer; ++m) s += (double)u[m] * (double)u[m];
     const double r = sqrt(block_sum_f64(s, red));
     double s2 = 0.0;
-    for (int i = t; i < npad; i += kNormThreads) {
-        double v = 0.0;
-        if (k < h && i < n && r > 0.0) v = (double)U[(int64_t)k * ldu + i] / r;
-        const el y = (el)v;
-        Yc[yc_index(k, i, npad)] = y;
-        Yr[yr_index(k, i, hp)] = y;
-        Ycs[ycs_index(k, i, hp)] = y;
-        if (uh64 && k < h && i < n) uh64[(int64_t)k * n + i] = v;
-        const double yd = (double)y;
-        s2 += yd * yd;
+#pragma unroll
+    for (int m = 0; m < kNormPer; ++m) {
+        const int i = t + kNormThreads * m;
+        if (i < npad) {
+            const double v = (live && i < n && r > 0.0) ? (double)u[m] / r : 0.0;
+            const el y = (el)v;
+            Yc[yc_index(k, i, npad)] = y;
+            Yr[yr_index(k, i, hp)] = y;
+            Ycs[ycs_index(k, i, hp)] = y;
+            if (uh64 && live && i < n) uh64[(int64_t)k * n + i] = v;
+            const double yd = (double)y;
+            s2 += yd * yd;
+        }
     }
     s2 = block_sum_f64(s2, red);
     if (t == 0) {
         nrm2[k] = s2;
-        if (nrm_raw) nrm_raw[k] = (k < h) ? r : 0.0;
+        if (nrm_raw) nrm_raw[k] = live ? r : 0.0;
     }
 }
 
-// Partial Gram matrices of the rounded reflectors in FP64 (a product of two
-// 16-bit values is exact): Gp[s][a][b] = sum over the rows of segment s of
-// y_a y_b, for the 16 x 16 tiles (ta, tb), ta <= tb, one block per (tile
-// pair, segment).  Each step stages the fragments (ta, q) and (tb, q) of the
-// fragment-ordered copy (32 rows each) in LDS.  With lam, the same pass also
-// forms Mp[s][a][b] = sum of y_a lam_r y_b (exact in FP64 too: 11 + 11 + 24
-// significant bits), the matrix Y^T diag(lam) Y of the symmetric form.
+// Partial Gram matrices of the rounded reflectors in FP64 on the matrix
+// cores: Gp[s][a][b] = sum over the rows of segment s of y_a y_b, for the
+// 16 x 16 tiles (ta, tb), ta <= tb, one wave per (tile pair, segment).  A
+// product of two 16-bit values is exact in FP64; with lam, a second set of
+// waves (blockIdx.z = 1) forms Mp[s][a][b] = sum of y_a lam_r y_b, the matrix
+// Y^T diag(lam) Y of the symmetric form, where lam_r y_b (24 + 11 significant
+// bits) and its product with y_a are exact too.  The FP64 MFMA (16 x 16 x 4) takes, per lane l = m + 16 k,
+// A[m][k] and B[k][m], and returns D[4 v + l / 16][l % 16] in element v.
+// Lane (c, g) of a fragment of the fragment-ordered copy holds the rows
+// 32q + 8g + j of reflector 16hb + c, so for each j it supplies A[c][g] from
+// tile ta and B[g][c] from tile tb, the same row behind K index g in both.
+// The chunks of 32 rows are fetched kGramGroup at a time, the next group's
+// loads in flight while the current one is multiplied.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kGramGroup = 4;
+
 template <typename E>
-__global__ __launch_bounds__(256) void k_wy_gram(const typename E::elem *__restrict__ Yc, int npad,
-                                                int hp, const float *__restrict__ lam,
-                                                double *__restrict__ Gp, double *__restrict__ Mp) {
+__global__ __launch_bounds__(kWave) void k_wy_gram(const typename E::elem *__restrict__ Yc, int npad,
+                                                  int hp, const float *__restrict__ lam,
+                                                  double *__restrict__ Gp, double *__restrict__ Mp) {
     using v8 = typename E::vec8;
-    __shared__ double ya[32][17], yb[32][17], lr[32];
+    constexpr int QG = kGramGroup;
     const int nhb = hp >> 4;
     int pr = blockIdx.x, ta = 0;
     while (pr >= nhb - ta) {
@@ -130,50 +148,84 @@ __global__ __launch_bounds__(256) void k_wy_gram(const typename E::elem *__restr
         ++ta;
     }
     const int tb = ta + pr;
-    const int nq = npad >> 5, qs = nq / kGramSeg, seg = blockIdx.y;
-    const int t = threadIdx.x, i = t >> 4, j = t & 15;
-    double acc = 0.0, accm = 0.0;
-    for (int q = seg * qs; q < (seg + 1) * qs; ++q) {
-        __syncthreads();
-        if (t < 128) {
-            const int which = t >> 6, ln = t & 63;
-            const int hb = which ? tb : ta;
-            const v8 v = *reinterpret_cast<const v8 *>(Yc + ((size_t)(hb * nq + q) * 64 + ln) * 8);
-            double(*dst)[17] = which ? yb : ya;
+    const int nq = npad >> 5, qs = nq / kGramSeg, q0 = blockIdx.y * qs, seg = blockIdx.y;
+    const int l = threadIdx.x, g = l >> 4;
+    const bool wl = blockIdx.z == 1;  // z = 0: G; z = 1 (with lam only): M
+    v8 ca[QG], cb[QG], na[QG], nb[QG];
+    f32x4 cl[QG][2], nl[QG][2];
+    auto fetch = [&](int grp, v8(&A)[QG], v8(&B)[QG], f32x4(&L)[QG][2]) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) dst[8 * (ln >> 4) + e][ln & 15] = (double)v[e];
-        } else if (lam && t < 160) {
-            lr[t - 128] = (double)lam[32 * q + t - 128];
-        }
-        __syncthreads();
-        if (lam) {
-#pragma unroll 8
-            for (int r = 0; r < 32; ++r) {
-                const double p = ya[r][i] * yb[r][j];
-                acc += p;
-                accm += p * lr[r];
+        for (int u = 0; u < QG; ++u) {
+            const int qq = grp * QG + u;
+            if (qq < qs) {
+                const int q = q0 + qq;
+                A[u] = *reinterpret_cast<const v8 *>(Yc + ((size_t)(ta * nq + q) * 64 + l) * 8);
+                B[u] = *reinterpret_cast<const v8 *>(Yc + ((size_t)(tb * nq + q) * 64 + l) * 8);
+                if (wl) {
+                    L[u][0] = *reinterpret_cast<const f32x4 *>(lam + 32 * q + 8 * g);
+                    L[u][1] = *reinterpret_cast<const f32x4 *>(lam + 32 * q + 8 * g + 4);
+                }
             }
-        } else {
-#pragma unroll 8
-            for (int r = 0; r < 32; ++r) acc += ya[r][i] * yb[r][j];
+        }
+    };
+    // two independent MFMA chains (j even, j odd)
+    f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+    const int ngrp = (qs + QG - 1) / QG;
+    fetch(0, ca, cb, cl);
+    for (int grp = 0; grp < ngrp; ++grp) {
+        if (grp + 1 < ngrp) fetch(grp + 1, na, nb, nl);
+#pragma unroll
+        for (int u = 0; u < QG; ++u) {
+            if (grp * QG + u < qs) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const double a = (double)ca[u][j];
+                    double bv = (double)cb[u][j];
+                    if (wl) bv *= (double)cl[u][j >> 2][j & 3];
+                    if (j & 1)
+                        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc1, 0, 0, 0);
+                    else
+                        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc0, 0, 0, 0);
+                }
+            }
+        }
+        if (grp + 1 < ngrp) {
+#pragma unroll
+            for (int u = 0; u < QG; ++u) {
+                ca[u] = na[u];
+                cb[u] = nb[u];
+                cl[u][0] = nl[u][0];
+                cl[u][1] = nl[u][1];
+            }
         }
     }
-    const size_t o = ((size_t)seg * hp + 16 * ta + i) * hp + 16 * tb + j;
-    Gp[o] = acc;
-    if (lam) Mp[o] = accm;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const size_t o = ((size_t)seg * hp + 16 * ta + 4 * v + g) * hp + 16 * tb + (l & 15);
+        (wl ? Mp : Gp)[o] = acc0[v] + acc1[v];
+    }
 }
 
-// T = (diag(||y_k||^2/2) + striu(G))^{-1}, upper triangular, FP64, by blocked
-// inversion in LDS: the 16 x 16 diagonal blocks are inverted by back
-// substitution (one column per thread), then neighbouring inverted blocks of
-// [A B; 0 C] are merged, the off-diagonal block becoming -A^{-1} (B C^{-1}),
-// doubling the block size at each level (each thread forms a 2 x 2 piece;
-// every element is accumulated in the same order whatever the thread count).
-// Outputs: Tw = T in FP64 (zero below the diagonal); Tf = T (tr = 0) and T^T (tr = 1) as 16-bit MFMA A-operand
-// fragments split into hi + lo parts (hi = T rounded, lo = the rest rounded)
-// for the streaming kernel's T product: fragment (tr, hl, ib, kb), lane (c, g),
-// element j holds T'[sigma_row(ib, c)][32 kb + 8 g + j].
-constexpr int kTmatThreads = 1024;
+// T = (diag(||y_k||^2/2) + striu(G))^{-1}, upper triangular, FP64, one column
+// per wave by back substitution, the columns of a block being 8 neighbours
+// (block b: columns 8b .. 8b+7).  With d_k the diagonal, column j solves
+// M x = e_j from the bottom: x_i is final once the rows below it are done, and
+// each x_i is then removed from the rows above (column-oriented form).  The
+// rows are kept scaled by 1/d_k, w_k = r_k / d_k, so x_i = w_i directly and a
+// step is one read of lane i and one FMA per row: w_k -= (G_ki / d_k) x_i.
+// The scaled coefficients G_ki / d_k (k < i, zero for k >= i) sit in LDS row
+// by row, row i holding column i of M, so the 64 lanes of a wave read one row
+// contiguously.  Steps run from i = j down to 0; lane k (and k + 64) holds
+// rows k (and k + 64).
+// Outputs: Tw = T in FP64 (zero below the diagonal); Tf = T (tr = 0) and T^T
+// (tr = 1) as 16-bit MFMA A-operand fragments split into hi + lo parts (hi = T
+// rounded, lo = the rest rounded) for the streaming kernel's T product:
+// fragment (tr, hl, ib, kb), lane (c, g), element j holds
+// T'[sigma_row(ib, c)][32 kb + 8 g + j].  Every such 8-element piece lies in
+// one block's 8 columns: for tr = 0 it is a row of them (32 kb + 8 g = 8 b),
+// for tr = 1 it is 8 rows of the column sigma_row(ib, c).
+constexpr int kTmatCols = 8;  // columns (waves) per block
+constexpr int kTmatThreads = kTmatCols * kWave;
 
 template <int HP, typename E>
 __global__ __launch_bounds__(kTmatThreads) void k_wy_tmat(const double *__restrict__ G,
@@ -181,107 +233,120 @@ __global__ __launch_bounds__(kTmatThreads) void k_wy_tmat(const double *__restri
                                                          double *__restrict__ Tw,
                                                          typename E::elem *__restrict__ Tf) {
     using el = typename E::elem;
-    constexpr int LD = HP + 1, NT = kTmatThreads;
-    extern __shared__ double M[];
-    const int t = threadIdx.x;
+    constexpr int LDN = HP + 1, HB = HP / 16, KS = HP / 32, SL = HP / kWave;
+    extern __shared__ double lds_t[];
+    double *sInv = lds_t;              // HP: 1 / d_k
+    double *sN = lds_t + HP;           // rows 0 .. cmax-1, LDN apart
+    const int t = threadIdx.x, lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int b = blockIdx.x, c0 = kTmatCols * b, cmax = c0 + kTmatCols;
+    if (t < HP) {
+        const double d = nrm2[t];
+        sInv[t] = 1.0 / (d > 0.0 ? 0.5 * d : 0.5);
+    }
+    __syncthreads();
+    // row i of sN = column i of M scaled: sN[i][k] = G[k][i] / d_k for k < i
+    // (rows i < cmax; thread t covers i = t % HP of rows k = t / HP + KST r,
+    // all its loads issued together)
+    {
+        constexpr int KST = kTmatThreads / HP, NR = HP / KST;
+        const int i = t % HP, k0 = t / HP;
+        if (i < cmax) {
+            double g[NR];
 #pragma unroll
-    for (int r = 0; r < (HP * HP + NT - 1) / NT; ++r) {
-        const int idx = t + r * NT;
-        if (idx < HP * HP) {
-            const int i = idx / HP, k = idx % HP;
-            const double g = G[idx];
-            const double d = nrm2[i];
-            M[i * LD + k] = k > i ? g : k < i ? 0.0 : (d > 0.0 ? 0.5 * d : 0.5);
+            for (int r = 0; r < NR; ++r) g[r] = G[(k0 + KST * r) * HP + i];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int k = k0 + KST * r;
+                const double v = g[r] * sInv[k];  // read for every k: no branch
+                sN[i * LDN + k] = k < i ? v : 0.0;
+            }
         }
     }
     __syncthreads();
-    {
-        const bool act = t < HP;  // HP / 16 blocks x 16 columns
-        const int o = 16 * (t >> 4), jc = t & 15;
-        double x[16];
-        if (act) {
+    const int j = c0 + wv;
+    double w[SL];
 #pragma unroll
-            for (int i = 15; i >= 0; --i) {
-                double s = (i == jc) ? 1.0 : 0.0;
+    for (int s = 0; s < SL; ++s) w[s] = (lane + kWave * s == j) ? sInv[j] : 0.0;
+    // steps i = j .. 64 read lane i - 64 of w[1] and touch both halves; steps
+    // below 64 read w[0] and leave rows >= 64 (all below the step) alone.
+    // Each phase starts at the next multiple of PF steps above j (still below
+    // cmax, as cmax - 64 s is a multiple of kTmatCols = PF): those extra steps
+    // read x = w_i = 0 and change nothing, and the PF-step body needs no
+    // branch.  Coefficient rows are read PF steps ahead.
+    constexpr int PF = kTmatCols;
 #pragma unroll
-                for (int k = i + 1; k < 16; ++k) s -= M[(o + i) * LD + o + k] * x[k];
-                x[i] = (i > jc) ? 0.0 : s / M[(o + i) * LD + o + i];
-            }
-        }
-        __syncthreads();
-        if (act) {
+    for (int s = SL - 1; s >= 0; --s) {
+        const int lo = kWave * s;
+        if (j < lo) continue;
+        const int ihi = lo + PF * ((std::min(j, lo + kWave - 1) - lo + PF) / PF) - 1;
+        double buf[PF][SL];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) M[(o + i) * LD + o + jc] = x[i];
-        }
-        __syncthreads();
-    }
+        for (int u = 0; u < PF; ++u)
 #pragma unroll
-    for (int s = 16; s < HP; s *= 2) {
-        const int th = s / 2;  // 2 x 2 pieces per row of an s x s block
-        const bool act = t < (HP / (2 * s)) * th * th;
-        const int pidx = t / (th * th), rr = t % (th * th);
-        const int i0 = 2 * s * pidx, a0 = i0 + 2 * (rr / th), b0 = i0 + s + 2 * (rr % th);
-        double acc[2][2];
-        for (int step = 0; step < 2; ++step) {
-            if (act) {
+            for (int q = 0; q <= s; ++q) buf[u][q] = sN[(ihi - u) * LDN + lane + kWave * q];
+        for (int i = ihi; i >= lo; i -= PF) {
 #pragma unroll
-                for (int q = 0; q < 2; ++q)
+            for (int u = 0; u < PF; ++u) {
+                const int ii = i - u, nx = std::max(ii - PF, 0);
+                double cur[SL];
 #pragma unroll
-                    for (int r = 0; r < 2; ++r) acc[q][r] = 0.0;
-                // step 0: B C^{-1} (C^{-1} at rows/cols i0+s..); step 1: A^{-1} X (X in B's place)
-                const int ka = step == 0 ? i0 + s : i0;
-#pragma unroll 8
-                for (int c = 0; c < s; ++c) {
-                    double av[2], bv[2];
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        av[q] = M[(a0 + q) * LD + ka + c];
-                        bv[q] = M[(ka + c) * LD + b0 + q];
-                    }
-#pragma unroll
-                    for (int q = 0; q < 2; ++q)
-#pragma unroll
-                        for (int r = 0; r < 2; ++r) acc[q][r] += av[q] * bv[r];
+                for (int q = 0; q <= s; ++q) {
+                    cur[q] = buf[u][q];
+                    buf[u][q] = sN[nx * LDN + lane + kWave * q];
                 }
-            }
-            __syncthreads();
-            if (act) {
-                const double sg = step == 0 ? 1.0 : -1.0;
+                const int src = ii - lo;
+                const int xl = __builtin_amdgcn_readlane(__double2loint(w[s]), src);
+                const int xh = __builtin_amdgcn_readlane(__double2hiint(w[s]), src);
+                const double x = __hiloint2double(xh, xl);
 #pragma unroll
-                for (int q = 0; q < 2; ++q)
-#pragma unroll
-                    for (int r = 0; r < 2; ++r) M[(a0 + q) * LD + b0 + r] = sg * acc[q][r];
+                for (int q = 0; q <= s; ++q) w[q] = fma(-cur[q], x, w[q]);
             }
-            __syncthreads();
         }
     }
+    __syncthreads();  // sN is done with: the 8 columns go to sT
+    double *sT = sN;  // sT[c][k] = T[k][c0 + c]
 #pragma unroll
-    for (int r = 0; r < (HP * HP + NT - 1) / NT; ++r) {
-        const int idx = t + r * NT;
-        if (idx < HP * HP) {
-            const int i = idx / HP, k = idx % HP;
-            const double v = (k >= i) ? M[i * LD + k] : 0.0;
-            Tw[idx] = v;
-        }
+    for (int s = 0; s < SL; ++s) sT[wv * HP + lane + kWave * s] = w[s];
+    __syncthreads();
+    for (int idx = t; idx < HP * kTmatCols; idx += kTmatThreads) {
+        const int k = idx / kTmatCols, c = idx % kTmatCols;
+        Tw[k * HP + c0 + c] = sT[c * HP + k];
     }
-    // fragments (the lower triangle of M is zero)
-    constexpr int HB = HP / 16, KS = HP / 32, NF = 4 * HB * KS * 64;
-    for (int id = t; id < NF; id += NT) {
-        const int lane = id & 63, f = id >> 6;
-        const int kb = f % KS, ib = (f / KS) % HB, hl = (f / (KS * HB)) & 1, tr = f / (2 * KS * HB);
-        const int c = lane & 15, g = lane >> 4;
-        const int row = sigma_row(ib, c);
+    // 4 HP pieces of 8 elements: tr = 0 (2 HP of them: hl, ib, c) then tr = 1 (hl, e, kb, g)
+    for (int p = t; p < 4 * HP; p += kTmatThreads) {
+        const int tr = p >= 2 * HP, pp = tr ? p - 2 * HP : p;
+        int hl, ib, c, kb, g;
+        double v[8];
+        if (!tr) {
+            hl = pp / HP;
+            ib = (pp % HP) / 16;
+            c = pp % 16;
+            kb = b / 4;
+            g = b % 4;
+            const int row = sigma_row(ib, c);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = sT[e * HP + row];
+        } else {
+            hl = pp / HP;
+            const int e = (pp % HP) / (4 * KS), r4 = pp % (4 * KS);
+            kb = r4 / 4;
+            g = r4 % 4;
+            const int row = c0 + e;  // sigma_row(ib, c) = row
+            ib = 2 * (row >> 5) + ((row >> 2) & 1);
+            c = 4 * ((row >> 3) & 3) + (row & 3);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = sT[e * HP + 32 * kb + 8 * g + q];
+        }
         typename E::vec8 fr;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int col = 32 * kb + 8 * g + j;
-            const double v = tr ? M[col * LD + row] : M[row * LD + col];
+        for (int q = 0; q < 8; ++q) {
             // through FP32: hi may differ from T's direct 16-bit rounding in a
             // tie, and lo = T - hi (formed in FP64) absorbs that
-            const el hi = (el)(float)v;
-            fr[j] = hl ? (el)(float)(v - (double)hi) : hi;
+            const el h16 = (el)(float)v[q];
+            fr[q] = hl ? (el)(float)(v[q] - (double)h16) : h16;
         }
-        *reinterpret_cast<typename E::vec8 *>(Tf + (size_t)id * 8) = fr;
+        const int f = ((tr * 2 + hl) * HB + ib) * KS + kb;
+        *reinterpret_cast<typename E::vec8 *>(Tf + ((size_t)f * 64 + c + 16 * g) * 8) = fr;
     }
 }
 
@@ -631,6 +696,7 @@ hipError_t wy_setup(const WyShape &s, const float *U, int64_t ldu, int64_t n, in
     using el = typename E::elem;
     const int hp = s.hp;
     const bool m = lam && want_m;
+    if (s.npad > kNormThreads * kNormPer) return hipErrorInvalidValue;  // k_wy_norm holds a row in registers
     if (lam)
         hipLaunchKernelGGL(k_fill_lam, dim3((s.npad + 255) / 256), dim3(256), 0, st, lam, (int)n, s.npad,
                            reinterpret_cast<float *>(ws + w.lam));
@@ -643,7 +709,7 @@ hipError_t wy_setup(const WyShape &s, const float *U, int64_t ldu, int64_t n, in
     const int nhb = hp / 16;
     const size_t hh = (size_t)hp * hp;
     double *gp = reinterpret_cast<double *>(ws + w.gram);
-    hipLaunchKernelGGL((k_wy_gram<E>), dim3(nhb * (nhb + 1) / 2, kGramSeg), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_wy_gram<E>), dim3(nhb * (nhb + 1) / 2, kGramSeg, m ? 2 : 1), dim3(kWave), 0, st,
                        reinterpret_cast<const el *>(ws + w.yc), s.npad, hp,
                        m ? reinterpret_cast<const float *>(ws + w.lam) : nullptr, gp,
                        m ? gp + kGramSeg * hh : nullptr);
@@ -654,11 +720,13 @@ hipError_t wy_setup(const WyShape &s, const float *U, int64_t ldu, int64_t n, in
         const double *n2 = reinterpret_cast<const double *>(ws + w.nrm2);
         double *tw = reinterpret_cast<double *>(ws + w.tw);
         el *tf = reinterpret_cast<el *>(ws + w.tf);
-        const size_t lds = (size_t)hp * (hp + 1) * 8;
+        // the last block holds all hp rows of the scaled coefficients
+        const size_t lds = ((size_t)hp + (size_t)hp * (hp + 1)) * 8;
+        const dim3 grid(hp / kTmatCols);
         if (hp == 64)
-            hipLaunchKernelGGL((k_wy_tmat<64, E>), dim3(1), dim3(kTmatThreads), lds, st, gs, n2, tw, tf);
+            hipLaunchKernelGGL((k_wy_tmat<64, E>), grid, dim3(kTmatThreads), lds, st, gs, n2, tw, tf);
         else
-            hipLaunchKernelGGL((k_wy_tmat<128, E>), dim3(1), dim3(kTmatThreads), lds, st, gs, n2, tw, tf);
+            hipLaunchKernelGGL((k_wy_tmat<128, E>), grid, dim3(kTmatThreads), lds, st, gs, n2, tw, tf);
     }
     const int nfrag = 4 * (hp / 16) * (hp / 32) * 64;
     if (m)
