@@ -115,6 +115,17 @@ def test_random_shape(algo, tname, op, n, h, N, seed):
                 if h > 0:
                     assert rel_fro(_host(dU), rdU) < gtol
                     assert rel_refl(_host(dU), rdU) < gtol, rel_refl(_host(dU), rdU)
+            if algo == "fused":  # the same through the record of dot products
+                d2, rec = P.mahal_raw(U, lam, X, Xb, save=True)
+                dXa2, _, dU2, dl2 = P.mahal_bwd_raw(U, lam, X, Xb, w, saved=rec)
+                torch.cuda.synchronize()
+                assert torch.equal(d2, d)
+                assert rel_rows(_host(dXa2), rdXa) < gtol
+                if N > 0:
+                    assert rel_fro(_host(dl2), rdl) < gtol
+                    if h > 0:
+                        assert rel_fro(_host(dU2), rdU) < gtol
+                        assert rel_refl(_host(dU2), rdU) < gtol, rel_refl(_host(dU2), rdU)
     except L.HHError as e:
         if _unsupported(e):
             pytest.skip(f"unsupported by the library: {e}")
