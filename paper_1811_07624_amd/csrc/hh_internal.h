@@ -93,27 +93,41 @@ template <int LPV, typename T> __device__ __forceinline__ T group_sum(T v) {
 }
 
 // out[y][e] = sum over q < nq of part[(y nq + q) stride + e], e < ne, in FP64
-// and in a fixed order (8 interleaved partial sums, then added 0..7).
-// Grid (ceil(ne / 32), number of independent sums y), 256 threads.
+// and in the order q = 0, 1, ...  Each thread sums 4 consecutive elements with
+// 16-byte loads, 8 partials in flight (ne and stride multiples of 4, part
+// 16-byte aligned).  Launched by launch_sum_parts.
+template <typename T> struct Vec4Of;
+template <> struct Vec4Of<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Vec4Of<double> { typedef double type __attribute__((ext_vector_type(4))); };
+constexpr int kSumThreads = 256;
 template <typename T>
-__global__ __launch_bounds__(256) void k_sum_parts(const T *__restrict__ part, int nq, size_t stride,
-                                                  int ne, double *__restrict__ out) {
-    __shared__ double red[8][32];
-    const int t = threadIdx.x, e = blockIdx.x * 32 + (t & 31), grp = t >> 5;
-    const T *p = part + (size_t)blockIdx.y * nq * stride;
-    double s = 0.0;
-    if (e < ne) {
-#pragma unroll 4
-        for (int q = grp; q < nq; q += 8) s += (double)p[(size_t)q * stride + e];
+__global__ __launch_bounds__(kSumThreads) void k_sum_parts(const T *__restrict__ part, int nq, size_t stride,
+                                                          int ne, double *__restrict__ out) {
+    using V = typename Vec4Of<T>::type;
+    const int e = 4 * (blockIdx.x * kSumThreads + threadIdx.x);
+    if (e >= ne) return;
+    const T *p = part + (size_t)blockIdx.y * nq * stride + e;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < nq; ++q) {
+        const V v = *reinterpret_cast<const V *>(p + (size_t)q * stride);
+        s0 += (double)v[0];
+        s1 += (double)v[1];
+        s2 += (double)v[2];
+        s3 += (double)v[3];
     }
-    red[grp][t & 31] = s;
-    __syncthreads();
-    if (t < 32 && e < ne) {
-        double v = 0.0;
-#pragma unroll
-        for (int g = 0; g < 8; ++g) v += red[g][t];
-        out[(size_t)blockIdx.y * ne + e] = v;
-    }
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    *reinterpret_cast<d4 *>(out + (size_t)blockIdx.y * ne + e) = d4{s0, s1, s2, s3};
+}
+
+// ny independent sums of nq partials of ne elements each (ne % 4 == 0).
+template <typename T>
+inline hipError_t launch_sum_parts(const T *part, int nq, size_t stride, int ne, int ny, double *out,
+                                   hipStream_t st) {
+    if (ne % 4 || stride % 4) return hipErrorInvalidValue;
+    const unsigned bx = (unsigned)((ne / 4 + kSumThreads - 1) / kSumThreads);
+    hipLaunchKernelGGL((k_sum_parts<T>), dim3(bx, ny), dim3(kSumThreads), 0, st, part, nq, stride, ne, out);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

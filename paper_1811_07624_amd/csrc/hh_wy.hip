@@ -713,8 +713,11 @@ hipError_t wy_setup(const WyShape &s, const float *U, int64_t ldu, int64_t n, in
                        reinterpret_cast<const el *>(ws + w.yc), s.npad, hp,
                        m ? reinterpret_cast<const float *>(ws + w.lam) : nullptr, gp,
                        m ? gp + kGramSeg * hh : nullptr);
-    hipLaunchKernelGGL((k_sum_parts<double>), dim3(hp * hp / 32, m ? 2 : 1), dim3(256), 0, st, gp, kGramSeg,
-                       hh, hp * hp, reinterpret_cast<double *>(ws + w.gsum));
+    {
+        const hipError_t e = launch_sum_parts<double>(gp, kGramSeg, hh, hp * hp, m ? 2 : 1,
+                                                      reinterpret_cast<double *>(ws + w.gsum), st);
+        if (e != hipSuccess) return e;
+    }
     {
         const double *gs = reinterpret_cast<const double *>(ws + w.gsum);
         const double *n2 = reinterpret_cast<const double *>(ws + w.nrm2);

@@ -631,21 +631,20 @@ hh_status wy_backward16(hh_op op, const hh_desc *d, const void *U, int64_t ldu, 
     const int hp = s.hp;
     const int kind = op == HH_OP_APPLY_BWD ? 0 : op == HH_OP_APPLY_T_BWD ? 1 : 2;
     const dim3 mg((hp * hp + 255) / 256);
-    hipLaunchKernelGGL((k_sum_parts<float>), dim3(hp * hp / 32, L.npairs), dim3(256), 0, st,
-                       reinterpret_cast<const float *>(base + L.gpart), L.ksg, (size_t)hp * hp, hp * hp,
-                       reinterpret_cast<double *>(base + L.kd));
+    e = launch_sum_parts<float>(reinterpret_cast<const float *>(base + L.gpart), L.ksg, (size_t)hp * hp, hp * hp,
+                                L.npairs, reinterpret_cast<double *>(base + L.kd), st);
+    if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY partial sums: %s", hipGetErrorString(e));
     hipLaunchKernelGGL(k_wy_mmat2, mg, dim3(256), 0, st, reinterpret_cast<const double *>(base + L.kd), hp,
                        kind, reinterpret_cast<double *>(base + L.ma), reinterpret_cast<double *>(base + L.mb),
                        reinterpret_cast<double *>(base + L.mc));
     {
         const size_t ne = (size_t)s.npad * L.m;
-        hipLaunchKernelGGL((k_sum_parts<float>), dim3((unsigned)((ne + 31) / 32), 1), dim3(256), 0, st,
-                           reinterpret_cast<const float *>(base + L.part), L.ks, ne, (int)ne,
-                           reinterpret_cast<double *>(base + L.psum));
-        if (sym)
-            hipLaunchKernelGGL((k_sum_parts<float>), dim3(s.npad / 32, 1), dim3(256), 0, st,
-                               reinterpret_cast<const float *>(base + L.gx), 4 * L.ks, (size_t)s.npad,
-                               s.npad, reinterpret_cast<double *>(base + L.gxsum));
+        e = launch_sum_parts<float>(reinterpret_cast<const float *>(base + L.part), L.ks, ne, (int)ne, 1,
+                                    reinterpret_cast<double *>(base + L.psum), st);
+        if (e == hipSuccess && sym)
+            e = launch_sum_parts<float>(reinterpret_cast<const float *>(base + L.gx), 4 * L.ks, (size_t)s.npad,
+                                        s.npad, 1, reinterpret_cast<double *>(base + L.gxsum), st);
+        if (e != hipSuccess) return set_error(HH_ERR_HIP, "WY partial sums: %s", hipGetErrorString(e));
     }
     CombineArgs ca{};
     ca.part = reinterpret_cast<const double *>(base + L.psum);
