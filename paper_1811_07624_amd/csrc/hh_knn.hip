@@ -58,7 +58,12 @@ __global__ __launch_bounds__(256) void k_knn_norms(const float *__restrict__ Z, 
 }
 
 // Split s of the database (tiles [t0, t1)) against 64 queries: the k best by
-// the expanded form, into part_d / part_i (row (s * Nq + q) * k).
+// the expanded form, into part_d / part_i (row (s * Nq + q) * k).  Thread t
+// fetches row t / 4 of a database tile, columns t % 4 + 4 i (i < np / 4 <=
+// PF), into registers; the next tile's fetch is issued as soon as the current
+// tile is in LDS, so it is in flight during the products, the screening and
+// the insertions.
+template <int PF>
 __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64_t ldq, int64_t Nq,
                                             const float *__restrict__ Zd, int64_t ldd, int64_t Nd,
                                             const float *__restrict__ qnorm, const float *__restrict__ dnorm,
@@ -99,14 +104,27 @@ __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64
     const int64_t ntiles = (Nd + kDB - 1) / kDB;
     const int64_t t0 = split * tiles_per_split;
     const int64_t t1 = t0 + tiles_per_split < ntiles ? t0 + tiles_per_split : ntiles;
+    const int lr = tid >> 2, lc = tid & 3, npf = np >> 2;
+    float pf[PF], pfn = 0.f;
+    auto fetch = [&](int64_t j0) {
+        const int64_t j = j0 + lr;
+        const float *src = Zd + (j < Nd ? j : 0) * ldd;
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int c = lc + 4 * i;
+            pf[i] = (i < npf && j < Nd && c < n) ? src[c] : 0.f;
+        }
+        if (tid < kDB) pfn = j0 + tid < Nd ? dnorm[j0 + tid] : 0.f;
+    };
+    if (t0 < t1) fetch(t0 * kDB);
     for (int64_t t = t0; t < t1; ++t) {
         const int64_t j0 = t * kDB;
         __syncthreads();  // previous tile's sD / sT / sMask readers are done
-        for (int e = tid; e < kDB * np; e += kKT) {
-            const int r = e / np, c = e % np;
-            sD[r * sq + c] = (j0 + r < Nd && c < n) ? Zd[(j0 + r) * ldd + c] : 0.f;
-        }
-        if (tid < kDB) sDn[tid] = j0 + tid < Nd ? dnorm[j0 + tid] : 0.f;
+#pragma unroll
+        for (int i = 0; i < PF; ++i)
+            if (i < npf) sD[lr * sq + lc + 4 * i] = pf[i];
+        if (tid < kDB) sDn[tid] = pfn;
+        if (t + 1 < t1) fetch(j0 + kDB);
         __syncthreads();
         f32x4 acc[2][2];
 #pragma unroll
@@ -247,14 +265,25 @@ __global__ __launch_bounds__(256) void k_knn_merge(const float *__restrict__ Zq,
     }
 }
 
-// Database splits: enough workgroups to fill the chip (about four per
-// compute unit), at most 16 splits, at least 4 tiles per split.
-int knn_splits(int64_t Nq, int64_t Nd) {
+// Database splits S: the workgroups (query blocks x S) run in rounds of
+// `cap` (LDS-limited workgroups per compute unit, at most 4, times the units),
+// each taking time in proportion to its tiles, so S minimises rounds x tiles
+// per split (fewer splits on ties; at most 16, at least 4 tiles per split).
+int knn_splits(int64_t Nq, int64_t Nd, int n, int k) {
     const int64_t qb = (Nq + kQB - 1) / kQB, ntiles = (Nd + kDB - 1) / kDB;
-    int64_t s = (4 * (int64_t)device_cu_count() + qb - 1) / qb;
-    s = std::min<int64_t>(s, 16);
-    s = std::min<int64_t>(s, std::max<int64_t>(1, ntiles / 4));
-    return (int)std::max<int64_t>(1, s);
+    const int np = (n + 3) / 4 * 4;
+    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(4, (160 * 1024) / (int64_t)knn_lds(np, k)));
+    const int64_t cap = per_cu * device_cu_count();
+    const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(16, ntiles / 4));
+    int64_t best = 1, bestc = -1;
+    for (int64_t sp = 1; sp <= smax; ++sp) {
+        const int64_t c = (qb * sp + cap - 1) / cap * ((ntiles + sp - 1) / sp);
+        if (bestc < 0 || c < bestc) {
+            bestc = c;
+            best = sp;
+        }
+    }
+    return (int)best;
 }
 
 // per-split lists (distances, indices), then the query and database norms
@@ -284,7 +313,7 @@ hh_status hh_knn_workspace_size(int64_t n, int64_t Nq, int64_t Nd, int64_t k, si
     if (!bytes) return set_error(HH_ERR_INVALID_ARG, "bytes must not be null");
     const hh_status s = knn_check(n, Nq, Nd, k);
     if (s != HH_OK) return s;
-    *bytes = Nq == 0 ? 0 : knn_ws_bytes(Nq, Nd, k, knn_splits(Nq, Nd));
+    *bytes = Nq == 0 ? 0 : knn_ws_bytes(Nq, Nd, k, knn_splits(Nq, Nd, (int)n, (int)k));
     return HH_OK;
 }
 
@@ -296,7 +325,7 @@ hh_status hh_knn(int64_t n, int64_t Nq, int64_t Nd, int64_t k, const float *Zq, 
     if (ldq < n || ldd < n) return set_error(HH_ERR_INVALID_ARG, "leading dimensions must be >= n");
     if (Nq == 0) return HH_OK;
     if (!Zq || !Zd || !dist || !idx || !ws) return set_error(HH_ERR_INVALID_ARG, "pointers must not be null");
-    const int S = knn_splits(Nq, Nd);
+    const int S = knn_splits(Nq, Nd, (int)n, (int)k);
     const size_t need = knn_ws_bytes(Nq, Nd, k, S);
     if (ws_bytes < need) return set_error(HH_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", need, ws_bytes);
     const int np = (int)((n + 3) / 4 * 4);
@@ -315,8 +344,18 @@ hh_status hh_knn(int64_t n, int64_t Nq, int64_t Nd, int64_t k, const float *Zq, 
     if (Nd > 0)
         hipLaunchKernelGGL(k_knn_norms, dim3((unsigned)((Nd + 255) / 256)), dim3(256), 0, st, Zd, ldd, Nd, (int)n,
                            dn);
-    hipLaunchKernelGGL(k_knn, dim3((unsigned)qblocks, (unsigned)S), dim3(kKT), lds, st, Zq, ldq, Nq, Zd,
-                       ldd, Nd, qn, dn, (int)n, np, (int)k, tps, pd, pi);
+    {
+        const dim3 grid((unsigned)qblocks, (unsigned)S);
+        if (np <= 48)
+            hipLaunchKernelGGL(k_knn<12>, grid, dim3(kKT), lds, st, Zq, ldq, Nq, Zd, ldd, Nd, qn, dn, (int)n, np,
+                               (int)k, tps, pd, pi);
+        else if (np <= 112)
+            hipLaunchKernelGGL(k_knn<28>, grid, dim3(kKT), lds, st, Zq, ldq, Nq, Zd, ldd, Nd, qn, dn, (int)n, np,
+                               (int)k, tps, pd, pi);
+        else
+            hipLaunchKernelGGL(k_knn<kMaxNk / 4>, grid, dim3(kKT), lds, st, Zq, ldq, Nq, Zd, ldd, Nd, qn, dn,
+                               (int)n, np, (int)k, tps, pd, pi);
+    }
     hipLaunchKernelGGL(k_knn_merge, dim3((unsigned)((Nq + 255) / 256)), dim3(256), 0, st, Zq, ldq, Nq, Zd,
                        ldd, (int)n, (int)k, S, pd, pi, dist, idx);
     const hipError_t e = hipGetLastError();
