@@ -201,17 +201,20 @@ __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64
     }
 }
 
-// One thread per query: merge the S split lists (each ascending, ties by
-// index) by (distance, index), recompute the k survivors' distances from the
-// differences, re-sort and write.
+// 16 lanes per query: every lane merges the S split lists (each ascending,
+// ties by index) by (distance, index) alike; the k survivors' distances are
+// recomputed from the differences, each lane summing coordinates r, r + 16,
+// ... in order and the 16 partial sums added by a fixed xor tree; then every
+// lane re-sorts and each lane writes the entries j with j % 16 = r.
 __global__ __launch_bounds__(256) void k_knn_merge(const float *__restrict__ Zq, int64_t ldq,
                                                   int64_t Nq, const float *__restrict__ Zd,
                                                   int64_t ldd, int n, int k, int S,
                                                   const float *__restrict__ part_d,
                                                   const int *__restrict__ part_i,
                                                   float *__restrict__ dist, int64_t *__restrict__ idx) {
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q >= Nq) return;
+    const int64_t q = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
+    const int r = threadIdx.x & 15;
+    if (q >= Nq) return;  // the whole 16-lane group
     float bd[kMaxK];
     int bi[kMaxK];
     int pos[16];
@@ -222,10 +225,10 @@ __global__ __launch_bounds__(256) void k_knn_merge(const float *__restrict__ Zq,
         int biv = 0x7fffffff;
         for (int s = 0; s < S; ++s) {
             if (pos[s] >= k) continue;
-            const int64_t r = ((int64_t)s * Nq + q) * k + pos[s];
-            const int x = part_i[r];
+            const int64_t row = ((int64_t)s * Nq + q) * k + pos[s];
+            const int x = part_i[row];
             if (x < 0) continue;
-            const float d = part_d[r];
+            const float d = part_d[row];
             if (d < bdv || (d == bdv && x < biv)) {
                 bdv = d;
                 biv = x;
@@ -241,10 +244,12 @@ __global__ __launch_bounds__(256) void k_knn_merge(const float *__restrict__ Zq,
         if (bi[j] < 0) continue;
         const float *b = Zd + (int64_t)bi[j] * ldd;
         float s = 0.f;
-        for (int c = 0; c < n; ++c) {
-            const float r = a[c] - b[c];
-            s = fmaf(r, r, s);
+        for (int c = r; c < n; c += 16) {
+            const float df = a[c] - b[c];
+            s = fmaf(df, df, s);
         }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
         bd[j] = s;
     }
     for (int j = 1; j < k; ++j) {  // insertion sort by (distance, index)
@@ -259,9 +264,12 @@ __global__ __launch_bounds__(256) void k_knn_merge(const float *__restrict__ Zq,
         bd[p] = d;
         bi[p] = x;
     }
-    for (int j = 0; j < k; ++j) {
-        dist[q * k + j] = bd[j];
-        idx[q * k + j] = bi[j];
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j) {
+        if (j < k && (j & 15) == r) {
+            dist[q * k + j] = bd[j];
+            idx[q * k + j] = bi[j];
+        }
     }
 }
 
@@ -331,7 +339,8 @@ hh_status hh_knn(int64_t n, int64_t Nq, int64_t Nd, int64_t k, const float *Zq, 
     const int np = (int)((n + 3) / 4 * 4);
     const size_t lds = knn_lds(np, (int)k);
     const int64_t qblocks = (Nq + kQB - 1) / kQB;
-    if (qblocks > ((int64_t)1 << 31) - 1) return set_error(HH_ERR_UNSUPPORTED, "too many queries");
+    if (qblocks > ((int64_t)1 << 31) - 1 || (Nq + 15) / 16 > ((int64_t)1 << 31) - 1)
+        return set_error(HH_ERR_UNSUPPORTED, "too many queries");
     const int64_t ntiles = (Nd + kDB - 1) / kDB;
     const int64_t tps = (ntiles + S - 1) / S;
     char *w = static_cast<char *>(ws);
@@ -356,7 +365,7 @@ hh_status hh_knn(int64_t n, int64_t Nq, int64_t Nd, int64_t k, const float *Zq, 
             hipLaunchKernelGGL(k_knn<kMaxNk / 4>, grid, dim3(kKT), lds, st, Zq, ldq, Nq, Zd, ldd, Nd, qn, dn,
                                (int)n, np, (int)k, tps, pd, pi);
     }
-    hipLaunchKernelGGL(k_knn_merge, dim3((unsigned)((Nq + 255) / 256)), dim3(256), 0, st, Zq, ldq, Nq, Zd,
+    hipLaunchKernelGGL(k_knn_merge, dim3((unsigned)((Nq * 16 + 255) / 256)), dim3(256), 0, st, Zq, ldq, Nq, Zd,
                        ldd, (int)n, (int)k, S, pd, pi, dist, idx);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? HH_OK : set_error(HH_ERR_HIP, "k-NN launch: %s", hipGetErrorString(e));
