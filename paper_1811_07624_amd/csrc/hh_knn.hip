@@ -14,10 +14,11 @@
 // compute unit);
 // each wave forms a 32 x 32
 // block of the 64 x 64 product tile (four 16 x 16 MFMA blocks, K = 4 per
-// step).  The distance tile goes through LDS, where all threads screen it
-// against each query's current k-th distance and one thread per query inserts
-// the survivors into its sorted k best (a candidate enters only when strictly
-// below the k-th, so among equal distances the earlier index stays).  A second
+// step).  Each lane screens its distances in registers against each query's
+// current k-th distance; only the candidates below it go to LDS, flagged in a
+// per-query survivor mask, and one thread per query inserts them in database
+// order into its sorted k best (a candidate enters only when strictly below
+// the k-th, so among equal distances the earlier index stays).  A second
 // kernel merges the splits' lists per query by (distance, index).  The
 // expanded form loses accuracy through cancellation when d_ij is small next to
 // ||a||^2 + ||b||^2, so the k survivors' distances are recomputed from the
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64
     float *sBd = sDn + kDB;                      // [kQB][k] best distances
     int *sBi = reinterpret_cast<int *>(sBd + kQB * k);  // [kQB][k] database indices
     float *sKth = reinterpret_cast<float *>(sBi + kQB * k);  // [kQB]
-    unsigned *sMask = reinterpret_cast<unsigned *>(sKth + kQB);  // [kQB][4] survivors
+    unsigned *sMask = reinterpret_cast<unsigned *>(sKth + kQB);  // [kQB][2] survivor bits by column
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t q0 = (int64_t)blockIdx.x * kQB;
@@ -97,10 +98,28 @@ __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64
             sBi[tid * k + j] = -1;
         }
         sKth[tid] = INFINITY;
+        sMask[tid * 2] = 0u;
+        sMask[tid * 2 + 1] = 0u;
     }
+    __syncthreads();
     // wave w: rows 32 (w / 2) .. +31, columns 32 (w % 2) .. +31 of the tile
     const int rb = 32 * (wv >> 1), cbk = 32 * (wv & 1);
     const int r16 = lane & 15, kk = lane >> 4;
+    float qn[2][4];  // norms of this lane's 8 query rows
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) qn[a][i] = sQn[rb + 16 * a + 4 * kk + i];
+    // for short vectors the queries' MFMA operands stay in registers
+    constexpr bool kQReg = PF <= 12;
+    float qa[2][kQReg ? PF : 1];
+    if constexpr (kQReg) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int ic = 0; ic < PF; ++ic)
+                qa[a][ic] = 4 * ic < np ? sQ[(rb + 16 * a + r16) * sq + 4 * ic + kk] : 0.f;
+    }
     const int64_t ntiles = (Nd + kDB - 1) / kDB;
     const int64_t t0 = split * tiles_per_split;
     const int64_t t1 = t0 + tiles_per_split < ntiles ? t0 + tiles_per_split : ntiles;
@@ -131,49 +150,58 @@ __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int c0 = 0; c0 < np; c0 += 4) {
-            float av[2], bv[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = sQ[(rb + 16 * a + r16) * sq + c0 + kk];
+        for (int ic = 0; ic < PF; ++ic) {
+            if (4 * ic < np) {
+                const int c0 = 4 * ic;
+                float av[2], bv[2];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = sD[(cbk + 16 * b + r16) * sq + c0 + kk];
+                for (int a = 0; a < 2; ++a) av[a] = kQReg ? qa[a][ic] : sQ[(rb + 16 * a + r16) * sq + c0 + kk];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) bv[b] = sD[(cbk + 16 * b + r16) * sq + c0 + kk];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+            }
+        }
+        // acc[a][b][i] is the product of query rb + 16 a + 4 kk + i and database
+        // vector cbk + 16 b + r16: each lane screens its 16 distances against
+        // the queries' k-th distance (as it stood before this tile) and writes
+        // only the candidates below it to the distance tile, flagging each in
+        // its query's 64-bit survivor mask
+        {
+            float dnv[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) dnv[b] = sDn[cbk + 16 * b + r16];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
-        }
-        // distance tile: acc[a][b][i] is the product of query rb + 16 a + 4 kk + i
-        // and database vector cbk + 16 b + r16
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int qr = rb + 16 * a + 4 * kk + i, dc = cbk + 16 * b + r16;
-                    const float d = sQn[qr] + sDn[dc] - 2.f * acc[a][b][i];
-                    sT[qr * (kDB + 1) + dc] = j0 + dc < Nd ? fmaxf(d, 0.f) : INFINITY;
+                    const int qr = rb + 16 * a + 4 * kk + i;
+                    const float kt = sKth[qr];
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        const int dc = cbk + 16 * b + r16;
+                        const float d = fmaxf(qn[a][i] + dnv[b] - 2.f * acc[a][b][i], 0.f);
+                        if (j0 + dc < Nd && d < kt) {
+                            sT[qr * (kDB + 1) + dc] = d;
+                            atomicOr(&sMask[qr * 2 + (dc >> 5)], 1u << (dc & 31));
+                        }
+                    }
                 }
-        __syncthreads();
-        // every thread screens 16 candidates of one query against its k-th
-        {
-            const int r = tid >> 2, c0 = 16 * (tid & 3);
-            const float kt = sKth[r];
-            unsigned m = 0;
-            for (int c = 0; c < 16; ++c)
-                if (sT[r * (kDB + 1) + c0 + c] < kt) m |= 1u << c;
-            sMask[r * 4 + (tid & 3)] = m;
         }
         __syncthreads();
         if (tid < kQB) {  // the owner inserts the survivors in database order
             float *bd = sBd + tid * k;
             int *bi = sBi + tid * k;
             float kth = sKth[tid];
-            for (int part = 0; part < 4; ++part) {
-                unsigned m = sMask[tid * 4 + part];
+            for (int part = 0; part < 2; ++part) {
+                unsigned m = sMask[tid * 2 + part];
+                sMask[tid * 2 + part] = 0u;
                 while (m) {
-                    const int c = 16 * part + __builtin_ctz(m);
+                    const int c = 32 * part + __builtin_ctz(m);
                     m &= m - 1;
                     const float d = sT[tid * (kDB + 1) + c];
                     if (!(d < kth)) continue;
