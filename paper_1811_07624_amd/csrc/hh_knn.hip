@@ -39,12 +39,19 @@ constexpr int kMaxNk = 224;  // keeps the LDS tiles within 160 KB at k = 32
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Up to this padded length the queries' MFMA operands are held in registers
+// after the start, and the distance tile reuses the queries' LDS space.
+constexpr int kQRegNp = 48;
+
 // LDS: queries [kQB][np+1], database tile [kDB][np+1], distance tile
-// [kQB][kDB+1], query norms, tile norms, the k best per query (dist, index),
-// the current k-th distance per query and the survivor masks.
+// [kQB][kDB+1] (over the queries when np <= kQRegNp), query norms, tile
+// norms, the k best per query (dist, index), the current k-th distance per
+// query and the survivor masks.
 __host__ __device__ inline size_t knn_lds(int np, int k) {
-    return ((size_t)kQB * (np + 1) + (size_t)kDB * (np + 1) + (size_t)kQB * (kDB + 1) + kQB + kDB) * 4 +
-           (size_t)kQB * k * 8 + (size_t)kQB * 4 + (size_t)kQB * 4 * 4;
+    const size_t q = (size_t)kQB * (np + 1), tt = (size_t)kQB * (kDB + 1);
+    const size_t qt = np <= kQRegNp ? (q > tt ? q : tt) : q + tt;
+    return (qt + (size_t)kDB * (np + 1) + kQB + kDB) * 4 + (size_t)kQB * k * 8 + (size_t)kQB * 4 +
+           (size_t)kQB * 4 * 4;
 }
 
 // Squared norms of the N vectors of Z (FP32 FMAs in coordinate order).
@@ -72,10 +79,12 @@ __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64
                                             float *__restrict__ part_d, int *__restrict__ part_i) {
     extern __shared__ __align__(16) float sm[];
     const int sq = np + 1;
-    float *sQ = sm;                              // [kQB][sq]
-    float *sD = sQ + kQB * sq;                   // [kDB][sq]
-    float *sT = sD + kDB * sq;                   // [kQB][kDB+1]
-    float *sQn = sT + kQB * (kDB + 1);           // [kQB]
+    constexpr bool kQReg = 4 * PF <= kQRegNp;  // queries' operands in registers
+    const int qsz = kQB * sq, tsz = kQB * (kDB + 1);
+    float *sQ = sm;                                               // [kQB][sq]
+    float *sD = sQ + (kQReg ? (qsz > tsz ? qsz : tsz) : qsz + tsz);  // [kDB][sq]
+    float *sT = kQReg ? sQ : sQ + qsz;                            // [kQB][kDB+1]
+    float *sQn = sD + kDB * sq;                                   // [kQB]
     float *sDn = sQn + kQB;                      // [kDB]
     float *sBd = sDn + kDB;                      // [kQB][k] best distances
     int *sBi = reinterpret_cast<int *>(sBd + kQB * k);  // [kQB][k] database indices
@@ -110,8 +119,8 @@ __global__ __launch_bounds__(kKT) void k_knn(const float *__restrict__ Zq, int64
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int i = 0; i < 4; ++i) qn[a][i] = sQn[rb + 16 * a + 4 * kk + i];
-    // for short vectors the queries' MFMA operands stay in registers
-    constexpr bool kQReg = PF <= 12;
+    // for short vectors the queries' MFMA operands stay in registers (sQ is
+    // then overwritten by the distance tile, after the first tile's barriers)
     float qa[2][kQReg ? PF : 1];
     if constexpr (kQReg) {
 #pragma unroll
@@ -383,8 +392,8 @@ hh_status hh_knn(int64_t n, int64_t Nq, int64_t Nd, int64_t k, const float *Zq, 
                            dn);
     {
         const dim3 grid((unsigned)qblocks, (unsigned)S);
-        if (np <= 48)
-            hipLaunchKernelGGL(k_knn<12>, grid, dim3(kKT), lds, st, Zq, ldq, Nq, Zd, ldd, Nd, qn, dn, (int)n, np,
+        if (np <= kQRegNp)
+            hipLaunchKernelGGL(k_knn<kQRegNp / 4>, grid, dim3(kKT), lds, st, Zq, ldq, Nq, Zd, ldd, Nd, qn, dn, (int)n, np,
                                (int)k, tps, pd, pi);
         else if (np <= 112)
             hipLaunchKernelGGL(k_knn<28>, grid, dim3(kKT), lds, st, Zq, ldq, Nq, Zd, ldd, Nd, qn, dn, (int)n, np,
