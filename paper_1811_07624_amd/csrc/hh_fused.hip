@@ -402,7 +402,10 @@ hipError_t dispatch(FusedOp op, const FusedPlan &p, const FusedFwdArgs &a, dim3 
         case 1: return launch_op<T, 16, 1>(op, p, a, grid, st);
         case 2: return launch_op<T, 16, 2>(op, p, a, grid, st);
         case 4: return launch_op<T, 16, 4>(op, p, a, grid, st);
-        case 8: return launch_op<T, 16, 8>(op, p, a, grid, st);
+        case 8:
+            if constexpr (std::is_same_v<T, float>)
+                if (p.s.vpl == 2) return launch_op<T, 16, 8, 2, 8>(op, p, a, grid, st);
+            return launch_op<T, 16, 8>(op, p, a, grid, st);
         case 16:
             if constexpr (std::is_same_v<T, float>)
                 if (p.s.vpl == 2) return launch_op<T, 16, 16, 2, 4>(op, p, a, grid, st);
@@ -468,11 +471,21 @@ bool fused_plan(hh_dtype t, int64_t n, int64_t h, int64_t N, FusedPlan *p, int n
     const size_t es = (t == HH_F64) ? 8 : 4;
     const size_t vec_bytes = (size_t)p->s.npad * es;
     const size_t fixed = vec_bytes * (1 + (size_t)ndiag);  // spectrum and the diagonals
-    size_t budget = (p->s.lpv == 64 && p->s.wpb == 8) ? kLdsBudgetWide : kLdsBudget;
+    size_t budget = p->s.wpb == 8 ? kLdsBudgetWide : kLdsBudget;
     // with diagonals, a large n runs with fewer blocks per compute unit
     if (ndiag > 0 && fixed + vec_bytes > budget) budget = kLdsBudgetWide;
     if (fixed + vec_bytes > budget) return false;
-    const int64_t fit = (int64_t)((budget - fixed) / vec_bytes);
+    int64_t fit = (int64_t)((budget - fixed) / vec_bytes);
+    if (t == HH_F32 && p->s.lpv == 16 && p->s.nc == 8 && p->s.vpl == 1 && h > fit) {
+        // more reflectors than one staging (e.g. QR's h = n - 1): every batch
+        // of vectors stages them all again, so 8-wave blocks with two vectors
+        // per lane group let each staged chunk (144 KB) serve 64 vectors
+        // instead of 16
+        p->s.vpl = 2;
+        p->s.wpb = 8;
+        budget = kLdsBudgetWide;
+        fit = (int64_t)((budget - fixed) / vec_bytes);
+    }
     p->hc = (int)std::max<int64_t>(1, std::min<int64_t>(h, fit));
     // reflectors, their tau and their leading zero chunk counts
     p->lds_bytes = fixed + (size_t)p->hc * (vec_bytes + es + sizeof(int));

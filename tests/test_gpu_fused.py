@@ -48,6 +48,7 @@ SHAPES = [
     (64, 4, 1024), (1, 1, 7), (2, 3, 5), (7, 2, 33), (63, 5, 100), (65, 5, 101),
     (100, 7, 257), (512, 9, 1000), (1000, 10, 129), (1023, 10, 65), (1024, 10, 1000),
     (1025, 3, 17), (2048, 16, 64), (4096, 64, 40), (4096, 3, 9), (513, 6, 31), (700, 12, 3),
+    (400, 50, 333),  # FP32: more reflectors than one LDS staging at n <= 512 (8-wave blocks)
 ]
 
 
