@@ -71,6 +71,27 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
     __syncthreads();
 
     const int nchunks = h > 0 ? (h + hc - 1) / hc : 0;
+    // copy `total` 16-byte pieces (piece i at offset at(i) in both) from the
+    // reflectors in memory to LDS, four loads of a thread in flight before
+    // their stores (a chunk is re-staged for every batch of vectors)
+    auto stage_pieces = [&](VT *dst, const VT *src, int total, auto at) {
+        int i = tid;
+        for (; i + 3 * kThreads < total; i += 4 * kThreads) {
+            VT v[4];
+            int o[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                o[u] = at(i + u * kThreads);
+                v[u] = src[o[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dst[o[u]] = v[u];
+        }
+        for (; i < total; i += kThreads) {
+            const int oi = at(i);
+            dst[oi] = src[oi];
+        }
+    };
     int loaded = -1;      // block-uniform
     int chunk_skip = 0;   // block-uniform: leading zero chunks shared by every reflector of the loaded chunk
     auto load_chunk = [&](int q) {
@@ -99,15 +120,13 @@ __global__ __launch_bounds__(WPB * kWave) void k_fused_fwd(FusedFwdArgs a) {
             chunk_skip = min(sLead[0] / G, NV - 1) * G;
             const int off = chunk_skip * (STR / W);  // skipped 16-byte pieces per reflector
             const int per = npad / W - off;
-            const int total = cnt * per;
-            for (int i = tid; i < total; i += kThreads) {
-                const int r = i / per, e = off + i % per;
-                dst[r * (npad / W) + e] = src[r * (npad / W) + e];
-            }
+            stage_pieces(dst, src, cnt * per, [&](int i) {
+                const int r = i / per;
+                return r * (npad / W) + off + (i - r * per);
+            });
             __syncthreads();
         } else {
-            const int total = cnt * (npad / W);
-            for (int i = tid; i < total; i += kThreads) dst[i] = src[i];
+            stage_pieces(dst, src, cnt * (npad / W), [](int i) { return i; });
             for (int i = tid; i < cnt; i += kThreads) sTau[i] = gTau[k0 + i];
             __syncthreads();
         }
