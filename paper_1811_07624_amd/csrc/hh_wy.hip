@@ -125,8 +125,9 @@ __global__ __launch_bounds__(kNormThreads) void k_wy_norm(const float *__restric
 // product of two 16-bit values is exact in FP64; with lam, a second set of
 // waves (blockIdx.z = 1) forms Mp[s][a][b] = sum of y_a lam_r y_b, the matrix
 // Y^T diag(lam) Y of the symmetric form, where lam_r y_b (24 + 11 significant
-// bits) and its product with y_a are exact too.  The FP64 MFMA (16 x 16 x 4) takes, per lane l = m + 16 k,
-// A[m][k] and B[k][m], and returns D[4 v + l / 16][l % 16] in element v.
+// bits) and its product with y_a are exact too.  The FP64 MFMA (16 x 16 x 4)
+// takes, from lane l = m + 16 k, A[m][k] and B[k][m], and returns
+// D[4 v + l / 16][l % 16] in element v of lane l.
 // Lane (c, g) of a fragment of the fragment-ordered copy holds the rows
 // 32q + 8g + j of reflector 16hb + c, so for each j it supplies A[c][g] from
 // tile ta and B[g][c] from tile tb, the same row behind K index g in both.
