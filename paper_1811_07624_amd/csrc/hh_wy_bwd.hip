@@ -406,27 +406,45 @@ __global__ __launch_bounds__(256, 2) void k_wy_combine(CombineArgs a) {
     }
 }
 
-// dU_k = (I - uh_k uh_k^T) dV_k / ||u_k||, one block per reflector.
-__global__ __launch_bounds__(256) void k_wy_finish(const double *__restrict__ dV, int npad, int n,
-                                                  const double *__restrict__ uh,
-                                                  const double *__restrict__ nrm, float *__restrict__ dU,
-                                                  int64_t lddu) {
-    __shared__ double red[256];
+// dU_k = (I - uh_k uh_k^T) dV_k / ||u_k||, one block per reflector, the row
+// held in registers (n <= kFinishThreads * kFinishPer = 8192, the compact-WY
+// limit; all loads of a thread issued together); uh_k^T dV_k summed by wave
+// shuffles, then the wave partials in a fixed order.
+constexpr int kFinishThreads = 1024, kFinishPer = 8;
+static_assert(kFinishThreads * kFinishPer >= 8192, "k_wy_finish must cover the compact-WY limit n <= 8192");
+__global__ __launch_bounds__(kFinishThreads) void k_wy_finish(const double *__restrict__ dV, int npad, int n,
+                                                             const double *__restrict__ uh,
+                                                             const double *__restrict__ nrm,
+                                                             float *__restrict__ dU, int64_t lddu) {
+    constexpr int NW = kFinishThreads / 64;
+    __shared__ double red[NW];
     const int k = blockIdx.x;
     const int t = threadIdx.x;
     const double *v = dV + (size_t)k * npad;
     const double *u = uh + (size_t)k * n;
-    double p = 0.0;
-    for (int e = t; e < n; e += 256) p += u[e] * v[e];
-    red[t] = p;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) red[t] += red[t + s];
-        __syncthreads();
+    double uu[kFinishPer], vv[kFinishPer];
+#pragma unroll
+    for (int m = 0; m < kFinishPer; ++m) {
+        const int e = t + kFinishThreads * m;
+        uu[m] = e < n ? u[e] : 0.0;
+        vv[m] = e < n ? v[e] : 0.0;
     }
-    p = red[0];
+    double p = 0.0;
+#pragma unroll
+    for (int m = 0; m < kFinishPer; ++m) p += uu[m] * vv[m];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+    if ((t & 63) == 0) red[t >> 6] = p;
+    __syncthreads();
+    p = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) p += red[w];
     const double nk = nrm[k];
-    for (int e = t; e < n; e += 256) dU[e + (int64_t)k * lddu] = nk > 0.0 ? (float)((v[e] - p * u[e]) / nk) : 0.f;
+#pragma unroll
+    for (int m = 0; m < kFinishPer; ++m) {
+        const int e = t + kFinishThreads * m;
+        if (e < n) dU[e + (int64_t)k * lddu] = nk > 0.0 ? (float)((vv[m] - p * uu[m]) / nk) : 0.f;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -664,7 +682,7 @@ hh_status wy_backward16(hh_op op, const hh_desc *d, const void *U, int64_t ldu, 
     if (hp == 64) hipLaunchKernelGGL(k_wy_combine<64>, dim3(s.npad / kCombineRows), dim3(256), 0, st, ca);
     else hipLaunchKernelGGL(k_wy_combine<128>, dim3(s.npad / kCombineRows), dim3(256), 0, st, ca);
     if (dU && h > 0)
-        hipLaunchKernelGGL(k_wy_finish, dim3((unsigned)h), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_wy_finish, dim3((unsigned)h), dim3(kFinishThreads), 0, st,
                            reinterpret_cast<const double *>(base + L.dv), s.npad, (int)n,
                            reinterpret_cast<const double *>(sb + L.base.uh64),
                            reinterpret_cast<const double *>(sb + L.base.nrmraw), static_cast<float *>(dU),
