@@ -42,7 +42,8 @@ def make(n, h, N, dt, seed=0):
 SHAPES = [(4096, 64, 1000), (256, 10, 33), (512, 9, 100), (1024, 64, 50), (2048, 100, 40),
           (8192, 128, 20), (4096, 1, 17), (1000, 7, 31), (64, 3, 5), (8192, 64, 300),
           (4096, 100, 129), (6144, 128, 257), (64, 100, 9), (32, 64, 40),  # these two: h > n
-          (6144, 50, 77)]  # resident kernel with 1024-row wave slices
+          (6144, 50, 77),  # resident kernel with 1024-row wave slices
+          (2000, 65, 37), (8184, 33, 21)]  # h padded 65 -> 128; n short of the largest padding
 
 
 @pytest.mark.parametrize("dname", ["bf16", "f16"])
