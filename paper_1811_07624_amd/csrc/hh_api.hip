@@ -211,6 +211,7 @@ static hh_status forward(hh_op op, const hh_desc *d, const void *U, int64_t ldu,
 
     FusedPlan p;
     HH_TRY(make_fused_plan(d, &p, (din ? 1 : 0) + (dout ? 1 : 0)));
+    if (saved) fused_plan_fit_record(&p);
     const FusedWs w = fused_ws(op, p);
     if (saved && saved_bytes < mahal_dots_bytes(d))
         return fail(HH_ERR_WORKSPACE, "record needs %zu bytes, got %zu", mahal_dots_bytes(d), saved_bytes);

@@ -499,7 +499,8 @@ bool fused_plan(hh_dtype t, int64_t n, int64_t h, int64_t N, FusedPlan *p, int n
         // more reflectors than one staging (e.g. QR's h = n - 1): every batch
         // of vectors stages them all again, so 8-wave blocks with two vectors
         // per lane group let each staged chunk (144 KB) serve 64 vectors
-        // instead of 16
+        // instead of 16 (the distance kernel's record staging is fitted
+        // beside it by fused_plan_fit_record)
         p->s.vpl = 2;
         p->s.wpb = 8;
         budget = kLdsBudgetWide;
@@ -509,6 +510,22 @@ bool fused_plan(hh_dtype t, int64_t n, int64_t h, int64_t N, FusedPlan *p, int n
     // reflectors, their tau and their leading zero chunk counts
     p->lds_bytes = fixed + (size_t)p->hc * (vec_bytes + es + sizeof(int));
     return true;
+}
+
+void fused_plan_fit_record(FusedPlan *p) {
+    // the distance kernel's record staging: hc values (padded to 16 bytes)
+    // per vector of the block, beside the plan's LDS, within 160 KB
+    constexpr size_t kLdsMax = 160 * 1024;
+    const size_t es = p->t == HH_F64 ? 8 : 4, rw = 16 / es;
+    const size_t vpb = (size_t)p->s.wpb * (kWave / p->s.lpv) * p->s.vpl;
+    const size_t per = (size_t)p->s.npad * es + es + sizeof(int);  // one staged reflector
+    const size_t fixed = p->lds_bytes - (size_t)p->hc * per;
+    while (p->hc > 1) {
+        const size_t hcp = ((size_t)p->hc + rw - 1) / rw * rw;
+        if (p->lds_bytes + 16 + vpb * hcp * es <= kLdsMax) break;
+        --p->hc;
+        p->lds_bytes = fixed + (size_t)p->hc * per;
+    }
 }
 
 hipError_t launch_fused_fwd(const FusedPlan &p, FusedOp op, const FusedFwdArgs &a,

@@ -199,5 +199,8 @@ hipError_t launch_fused_fwd(const FusedPlan &p, FusedOp op, const FusedFwdArgs &
 // ndiag: how many n-vectors of diagonal entries the kernel stages beside the
 // spectrum (0, 1 or 2)
 bool fused_plan(hh_dtype t, int64_t n, int64_t h, int64_t N, FusedPlan *p, int ndiag = 0);
+// For the distance kernel with its record of dot products: fewer reflectors
+// per LDS staging where the record's staging would not fit beside them.
+void fused_plan_fit_record(FusedPlan *p);
 
 }  // namespace hh

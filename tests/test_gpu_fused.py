@@ -227,7 +227,8 @@ def test_fused_bwd_fp32_n4096_h64(op):
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("n,h,N", [(512, 9, 1000), (100, 7, 129), (1024, 40, 30), (33, 0, 10),
-                                   (7, 3, 5), (64, 4, 0)])
+                                   (7, 3, 5), (64, 4, 0),
+                                   (400, 90, 77)])  # FP32: 8-wave staging plan, record in two chunks
 def test_mahal_bwd_from_record(dtype, n, h, N):
     """Distances with the record of dot products (hh_mahalanobis_save) equal the
     plain ones exactly, and the backward from the record meets the oracle to the
